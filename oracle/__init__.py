@@ -1,0 +1,255 @@
+"""CPU oracle for the divide-and-conquer sampler -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle.so`` (built from
+``dcs_oracle.c`` with gcc, contraction off) through ctypes and shares no code
+with the HIP library in ``paper_1610_05141_amd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "dcs_oracle.c")
+
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+          "-shared", "-fvisibility=hidden", "-Wall", "-Wextra"]
+
+# Stream purposes (same meaning as the library's; restated here on purpose).
+P_SPLIT, P_LEAF, P_BERN, P_REPAIR, P_BCHUNK, P_WRSPLIT, P_WRLEAF = 1, 2, 3, 4, 5, 6, 7
+
+DEFAULT_N0 = 4096
+DEFAULT_DENSE_RATIO = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (idempotent unless ``force``)."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC_PATH, "-lm"], check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, i32, dbl, flt = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_float)
+        p64 = ctypes.POINTER(ctypes.c_uint64)
+        p32 = ctypes.POINTER(ctypes.c_uint32)
+        sig = {
+            "dcs_ref_sample": (i32, [u64, u64, u64, u32, u32, p64]),
+            "dcs_ref_sample_window": (i32, [u64, u64, u64, u32, u32, u64, u64, p64]),
+            "dcs_ref_replacement": (i32, [u64, u64, u64, u32, p64]),
+            "dcs_ref_replacement_window": (i32, [u64, u64, u64, u32, u64, u64, p64]),
+            "dcs_ref_bernoulli": (i32, [dbl, u64, u64, u32, p64, u64, p64]),
+            "dcs_ref_bernoulli_chunks": (i32, [dbl, u64, u64, u32, u64, u64, p64, u64, p64]),
+            "dcs_ref_bernoulli_chunk_len": (u64, [dbl, u32]),
+            "dcs_ref_philox": (None, [p32, p32, p32]),
+            "dcs_ref_stream_word": (u32, [u64, u64, u32, u32, u64]),
+            "dcs_ref_stream_draw64": (u64, [u64, u64, u32, u32, u64]),
+            "dcs_ref_range_map": (ctypes.c_int64, [u32, u64]),
+            "dcs_ref_log64": (dbl, [dbl]),
+            "dcs_ref_log1p64": (dbl, [dbl]),
+            "dcs_ref_log32": (flt, [flt]),
+            "dcs_ref_u32_geom": (flt, [u32]),
+            "dcs_ref_lnfact_diff": (dbl, [u64, u64]),
+            "dcs_ref_hyp": (u64, [u64, u64, u64, u64, u64]),
+            "dcs_ref_bin": (u64, [u64, u64, u64, u64, u64]),
+            "dcs_ref_tree_stats": (i32, [u64, u64, u64, u32, p64]),
+            "dcs_ref_log32_batch": (None, [ctypes.c_void_p, u64, ctypes.c_void_p]),
+            "dcs_ref_log64_batch": (None, [ctypes.c_void_p, u64, ctypes.c_void_p]),
+            "dcs_ref_log1p64_batch": (None, [ctypes.c_void_p, u64, ctypes.c_void_p]),
+            "dcs_ref_lnfact_diff_batch": (None, [ctypes.c_void_p, ctypes.c_void_p, u64,
+                                                 ctypes.c_void_p]),
+            "dcs_ref_hyp_batch": (None, [u64, u64, u64, u64, u64, u64, p64]),
+            "dcs_ref_bin_batch": (None, [u64, u64, u64, u64, u64, u64, p64]),
+            "dcs_ref_range_map_counts": (None, [u64, p64, p64]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p64(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def sample(n: int, N: int, seed: int, n0: int = DEFAULT_N0,
+           dense_ratio: int = DEFAULT_DENSE_RATIO) -> np.ndarray:
+    """n distinct values of 1..N, ascending (Algorithm R, Fig. 1)."""
+    out = np.empty(n, dtype=np.uint64)
+    _check(lib().dcs_ref_sample(n, N, seed, n0, dense_ratio, _p64(out)), "sample")
+    return out
+
+
+def sample_window(n: int, N: int, seed: int, start: int, count: int,
+                  n0: int = DEFAULT_N0, dense_ratio: int = DEFAULT_DENSE_RATIO) -> np.ndarray:
+    """out[start:start+count] of ``sample(n, N, seed)``, visiting only the
+    subtrees whose output overlaps the window."""
+    out = np.empty(count, dtype=np.uint64)
+    _check(lib().dcs_ref_sample_window(n, N, seed, n0, dense_ratio, start, count, _p64(out)),
+           "sample_window")
+    return out
+
+
+def replacement(n: int, N: int, seed: int, n0: int = DEFAULT_N0) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint64)
+    _check(lib().dcs_ref_replacement(n, N, seed, n0, _p64(out)), "replacement")
+    return out
+
+
+def replacement_window(n: int, N: int, seed: int, start: int, count: int,
+                       n0: int = DEFAULT_N0) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    _check(lib().dcs_ref_replacement_window(n, N, seed, n0, start, count, _p64(out)),
+           "replacement_window")
+    return out
+
+
+def bernoulli(p: float, N: int, seed: int, n0: int = DEFAULT_N0,
+              capacity: int | None = None) -> np.ndarray:
+    if capacity is None:
+        capacity = int(N * p + 10 * (N * p * (1 - p)) ** 0.5 + 64) if p < 1 else N
+    out = np.empty(max(capacity, 1), dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().dcs_ref_bernoulli(float(p), N, seed, n0, _p64(out), capacity, _p64(cnt))
+    _check(rc, "bernoulli")
+    return out[: int(cnt[0])].copy()
+
+
+def bernoulli_chunks(p: float, N: int, seed: int, chunk_lo: int, chunk_hi: int,
+                     n0: int = DEFAULT_N0, capacity: int = 1 << 20) -> np.ndarray:
+    out = np.empty(capacity, dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().dcs_ref_bernoulli_chunks(float(p), N, seed, n0, chunk_lo, chunk_hi,
+                                        _p64(out), capacity, _p64(cnt))
+    _check(rc, "bernoulli_chunks")
+    return out[: int(cnt[0])].copy()
+
+
+def bernoulli_chunk_len(p: float, n0: int = DEFAULT_N0) -> int:
+    return int(lib().dcs_ref_bernoulli_chunk_len(float(p), n0))
+
+
+def philox(ctr, key) -> tuple:
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().dcs_ref_philox(c, k, o)
+    return tuple(o)
+
+
+def stream_word(seed, node_id, purpose, attempt, t) -> int:
+    return int(lib().dcs_ref_stream_word(seed, node_id, purpose, attempt, t))
+
+
+def stream_draw64(seed, node_id, purpose, attempt, t) -> int:
+    return int(lib().dcs_ref_stream_draw64(seed, node_id, purpose, attempt, t))
+
+
+def range_map(w: int, s: int) -> int:
+    return int(lib().dcs_ref_range_map(w, s))
+
+
+def log64(x: float) -> float:
+    return lib().dcs_ref_log64(x)
+
+
+def log1p64(x: float) -> float:
+    return lib().dcs_ref_log1p64(x)
+
+
+def log32(x: float) -> float:
+    return lib().dcs_ref_log32(x)
+
+
+def u32_geom(w: int) -> float:
+    return lib().dcs_ref_u32_geom(w)
+
+
+def lnfact_diff(a: int, b: int) -> float:
+    return lib().dcs_ref_lnfact_diff(a, b)
+
+
+def hyp(n: int, M: int, N: int, seed: int, node_id: int) -> int:
+    return int(lib().dcs_ref_hyp(n, M, N, seed, node_id))
+
+
+def binom(n: int, l: int, Nv: int, seed: int, node_id: int) -> int:
+    return int(lib().dcs_ref_bin(n, l, Nv, seed, node_id))
+
+
+def tree_stats(n: int, N: int, seed: int, n0: int = DEFAULT_N0) -> tuple:
+    st = np.zeros(3, dtype=np.uint64)
+    _check(lib().dcs_ref_tree_stats(n, N, seed, n0, _p64(st)), "tree_stats")
+    return int(st[0]), int(st[1]), int(st[2])
+
+
+def log32_batch(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty_like(x)
+    lib().dcs_ref_log32_batch(x.ctypes.data, x.size, y.ctypes.data)
+    return y
+
+
+def log64_batch(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    lib().dcs_ref_log64_batch(x.ctypes.data, x.size, y.ctypes.data)
+    return y
+
+
+def log1p64_batch(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    lib().dcs_ref_log1p64_batch(x.ctypes.data, x.size, y.ctypes.data)
+    return y
+
+
+def lnfact_diff_batch(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    y = np.empty(a.size, dtype=np.float64)
+    lib().dcs_ref_lnfact_diff_batch(a.ctypes.data, b.ctypes.data, a.size, y.ctypes.data)
+    return y
+
+
+def hyp_batch(n: int, M: int, N: int, seed: int, id0: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    lib().dcs_ref_hyp_batch(n, M, N, seed, id0, count, _p64(out))
+    return out
+
+
+def binom_batch(n: int, l: int, Nv: int, seed: int, id0: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    lib().dcs_ref_bin_batch(n, l, Nv, seed, id0, count, _p64(out))
+    return out
+
+
+def range_map_counts(s: int) -> tuple:
+    counts = np.zeros(s, dtype=np.uint64)
+    voids = np.zeros(1, dtype=np.uint64)
+    lib().dcs_ref_range_map_counts(s, _p64(counts), _p64(voids))
+    return counts, int(voids[0])
