@@ -1,0 +1,188 @@
+/*
+ * dcs.h -- C ABI of the MI355X divide-and-conquer random sampler.
+ *
+ * Method: Sanders, Lamm, Huebschle-Schneider, Schrade, Dachsbacher,
+ * "Efficient Parallel Random Sampling -- Vectorized, Cache-Efficient, and
+ * Online", ACM TOMS 44(3), 2018.
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named *_dev are device (HBM) pointers on the current HIP
+ *     device; the caller allocates and owns them.  The library never frees
+ *     caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued asynchronously on it; nothing blocks the host unless
+ *     the entry point says so.
+ *   - Output values are 1-based (elements of 1..N) as uint64, ascending.
+ *   - Return value: a dcs_status code.  Device-side failures (a capacity
+ *     bound exceeded inside a kernel) cannot be returned by an asynchronous
+ *     call; they are latched in a device error word and reported by
+ *     dcs_synchronize() on that stream.
+ *   - The sample is a pure function of (variant, n or p, N, seed, n0,
+ *     dense_ratio): launch geometry, batch composition and arrival order never
+ *     change a bit of it (paper Sec. 4.5, strengthened: no dependence on the
+ *     number of processing elements either).
+ */
+#ifndef DCS_H_
+#define DCS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dcs_status {
+  DCS_OK = 0,
+  DCS_EINVAL = 1,    /* invalid argument (see each entry point) */
+  DCS_ENOMEM = 2,    /* workspace too small / device allocation failed */
+  DCS_EHIP = 3,      /* a HIP runtime call failed */
+  DCS_EOVERFLOW = 4, /* Bernoulli: more hits than `capacity` */
+  DCS_EDEVICE = 5,   /* a kernel latched an error (reported at synchronize) */
+  DCS_ENOTSUP = 6    /* request outside what this build supports */
+} dcs_status;
+
+/* Largest universe N accepted (every integer entering a double stays exact). */
+#define DCS_MAX_UNIVERSE (1ull << 52)
+
+/* Canonical parameters: part of the sample's identity (changing one changes
+ * the sample).  Pass NULL for the defaults. */
+typedef struct dcs_params {
+  uint32_t struct_size; /* sizeof(dcs_params) */
+  uint32_t n0;          /* base-case threshold: a node splits iff n_v >= n0
+                           (Fig. 1, "if n < n0 then return sampleBase");
+                           2 <= n0 <= 4096, default 4096 */
+  uint32_t dense_ratio; /* a leaf uses Algorithm B iff dense_ratio*n_v >= N_v,
+                           else Algorithm H; 2..64, default 16 */
+  uint32_t reserved;
+} dcs_params;
+
+/*
+ * dcs_sample -- n distinct integers drawn uniformly from 1..N, ascending
+ * (paper Sec. 1-2: the problem statement; Sec. 3.1 Fig. 1: Algorithm R;
+ * Sec. 3.2: the node-identity hash of Algorithm P; Sec. 4.1: sorted output).
+ *   out_dev: n uint64 values (8n bytes), device memory, written in full.
+ * Errors: DCS_EINVAL if n > N, N > DCS_MAX_UNIVERSE, out_dev == NULL with
+ * n > 0, or bad params.  n == 0 writes nothing.  Uses a per-device workspace
+ * that the library grows on demand (hipMalloc; may synchronize the device).
+ */
+int32_t dcs_sample(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev, void* stream);
+
+/* dcs_sample with explicit canonical params and an optional caller
+ * workspace (workspace == NULL: the library's own).  ws_bytes must be at
+ * least dcs_workspace_size(0, n, N, params); DCS_ENOMEM otherwise. */
+int32_t dcs_sample_ex(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                      uint64_t* out_dev, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * dcs_sample_replacement -- n integers drawn independently and uniformly
+ * from 1..N, sorted non-decreasing, repeats kept (Sec. 4.6: Algorithm R with
+ * a binomial instead of a hypergeometric split).
+ * Errors: DCS_EINVAL if N == 0 with n > 0, N > DCS_MAX_UNIVERSE, NULL out.
+ */
+int32_t dcs_sample_replacement(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev,
+                               void* stream);
+int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed,
+                                  const dcs_params* params, uint64_t* out_dev, void* workspace,
+                                  size_t ws_bytes, void* stream);
+
+/*
+ * dcs_sample_bernoulli -- each element of 1..N is kept independently with
+ * probability p; the kept elements ascending (Sec. 4.7: Bernoulli sampling
+ * applied independently to fixed subranges -- chunks of
+ * 2^floor(log2(n0/p)) elements clamped to [2^12, 2^32] -- each by
+ * geometric skips and prefix sums).
+ *   out_dev:   capacity uint64 slots; the first min(count, capacity) values
+ *              are written.
+ *   count_dev: one uint64 in device memory, receives the true count.
+ * Errors: DCS_EINVAL if p is NaN or outside [0,1], N > DCS_MAX_UNIVERSE, or
+ * a NULL pointer where one is needed.  A count above `capacity` is not an
+ * error of the call (it cannot be known when the call returns): compare
+ * *count_dev with capacity after synchronizing; re-running with a larger
+ * buffer gives the identical sample.
+ */
+int32_t dcs_sample_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t* out_dev,
+                             uint64_t capacity, uint64_t* count_dev, void* stream);
+int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_params* params,
+                                uint64_t* out_dev, uint64_t capacity, uint64_t* count_dev,
+                                void* workspace, size_t ws_bytes, void* stream);
+/* A capacity that the Bernoulli count exceeds with negligible probability:
+ * Np + 10 sqrt(Np(1-p)) + 64. */
+uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N);
+
+/* Workspace bytes needed.  variant: 0 = without replacement (n = sample
+ * size), 1 = with replacement, 2 = Bernoulli (n ignored, p given as
+ * p_for_bernoulli).  Writes *bytes; DCS_EINVAL on bad arguments. */
+int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for_bernoulli,
+                           const dcs_params* params, size_t* bytes);
+
+/*
+ * Batched sampling: many independent instances of uneven (n, N) in one
+ * launch sequence (Sec. 4.2: many atomic jobs dynamically assigned to
+ * workers; Sec. 4.5: results independent of that assignment).  Instance i
+ * writes its sample to out_dev + out_offset[i].  Each instance's output is
+ * bit-identical to a dcs_sample_ex / dcs_sample_replacement_ex call with the
+ * same (n, N, seed, n0, dense_ratio).
+ */
+typedef struct dcs_instance {
+  uint64_t n;
+  uint64_t N;
+  uint64_t seed;
+  uint64_t out_offset; /* in uint64 elements from out_dev */
+  uint32_t variant;    /* 0 = without replacement, 1 = with replacement */
+  uint32_t n0;         /* 0 = default */
+  uint32_t dense_ratio;/* 0 = default */
+  uint32_t reserved;
+} dcs_instance;
+
+typedef struct dcs_batch dcs_batch; /* opaque */
+
+/* Validates and uploads the instance table (host array of `count`) and
+ * sizes the batch's device workspace.  The table is copied.  Errors:
+ * DCS_EINVAL for an invalid instance (its index in *bad_index if non-NULL). */
+int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batch** batch,
+                         uint32_t* bad_index);
+/* Enqueues the whole batch on `stream`.  use_graph != 0: the launches are
+ * captured once into a hipGraph and replayed on later calls. */
+int32_t dcs_batch_run(dcs_batch* batch, uint64_t* out_dev, int32_t use_graph, void* stream);
+int32_t dcs_batch_destroy(dcs_batch* batch);
+/* Total output elements of the batch (sum of n). */
+uint64_t dcs_batch_total(const dcs_batch* batch);
+
+/* Waits for `stream`, then reports and clears any error latched by the
+ * library's kernels: DCS_EDEVICE if one was latched, else DCS_OK. */
+int32_t dcs_synchronize(void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* dcs_status_string(int32_t status);
+
+/* Kernel timing with HIP events recorded on the stream each kernel is
+ * launched on.  enable != 0 starts recording (and clears the totals).
+ * dcs_profile_read: after the stream is synchronized, accumulated
+ * milliseconds and launch count for kernel `kind`
+ * (0 = reset, 1 = tree split, 2 = leaf, 3 = Bernoulli chunk). */
+int32_t dcs_profile_enable(int32_t enable);
+int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
+
+/*
+ * Diagnostics: the device primitives applied elementwise to device arrays,
+ * so that tests can compare them bit for bit with an independent CPU
+ * implementation.  All arrays are device memory of `count` elements; the
+ * call is asynchronous on `stream`.
+ *   op 0: y_f64 = ln(x_f64)            op 1: y_f64 = ln(1 + x_f64)
+ *   op 2: y_f32 = ln(x_f32)            op 3: y_f64 = sqrt(x_f64)
+ *   op 4: y_f64 = x_f64 / x2_f64       op 5: y_f64 = ln(a!) - ln(b!) (a = x_u64, b = x2_u64)
+ *   op 6: y_u64 = Hyp(n, M, N) for node ids x_u64, params p0..p2 = n, M, N, p3 = seed
+ *   op 7: y_u64 = Bin(n, l/Nv) for node ids x_u64, params p0..p2 = n, l, Nv, p3 = seed
+ *   op 8: y_u32[4i..4i+3] = Philox block of counter x_u32[4i..4i+3], key (p0, p1)
+ *   op 9: y_f32 = U of the geometric skip for word x_u32
+ */
+int32_t dcs_debug_primitive(int32_t op, const void* x_dev, const void* x2_dev, void* y_dev,
+                            uint64_t count, uint64_t p0, uint64_t p1, uint64_t p2, uint64_t p3,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCS_H_ */

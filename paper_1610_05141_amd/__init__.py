@@ -1,0 +1,246 @@
+"""Python binding of the MI355X divide-and-conquer sampler (libdcs.so).
+
+Argument marshalling only: every step of the sampler runs in the library's
+HIP kernels.  torch supplies device memory and streams.  Importing works
+without a GPU; calling anything that needs the library raises if
+``_lib/libdcs.so`` has not been built (``python paper_1610_05141_amd/build.py``
+or ``__graft_entry__.build()``) -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "synchronize",
+    "workspace_size", "bernoulli_capacity_hint", "Batch", "profile_enable", "profile_read",
+    "debug_primitive", "EXPORTED_SYMBOLS", "LIB_PATH",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libdcs.so")
+
+DCS_OK, DCS_EINVAL, DCS_ENOMEM, DCS_EHIP, DCS_EOVERFLOW, DCS_EDEVICE, DCS_ENOTSUP = range(7)
+
+# Every symbol declared in include/dcs.h.
+EXPORTED_SYMBOLS = (
+    "dcs_sample", "dcs_sample_ex", "dcs_sample_replacement", "dcs_sample_replacement_ex",
+    "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
+    "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
+    "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
+    "dcs_profile_read", "dcs_debug_primitive",
+)
+
+
+class DcsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = lib().dcs_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} (status {code})")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n0", ctypes.c_uint32),
+                ("dense_ratio", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("N", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("out_offset", ctypes.c_uint64), ("variant", ctypes.c_uint32),
+                ("n0", ctypes.c_uint32), ("dense_ratio", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdcs.so (raises FileNotFoundError if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with `python paper_1610_05141_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, i32, dbl, vp = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_void_p)
+        pp = ctypes.POINTER(_Params)
+        sig = {
+            "dcs_sample": (i32, [u64, u64, u64, vp, vp]),
+            "dcs_sample_ex": (i32, [u64, u64, u64, pp, vp, vp, ctypes.c_size_t, vp]),
+            "dcs_sample_replacement": (i32, [u64, u64, u64, vp, vp]),
+            "dcs_sample_replacement_ex": (i32, [u64, u64, u64, pp, vp, vp, ctypes.c_size_t, vp]),
+            "dcs_sample_bernoulli": (i32, [dbl, u64, u64, vp, u64, vp, vp]),
+            "dcs_sample_bernoulli_ex": (i32, [dbl, u64, u64, pp, vp, u64, vp, vp,
+                                              ctypes.c_size_t, vp]),
+            "dcs_bernoulli_capacity_hint": (u64, [dbl, u64]),
+            "dcs_workspace_size": (i32, [i32, u64, u64, dbl, pp, ctypes.POINTER(ctypes.c_size_t)]),
+            "dcs_batch_create": (i32, [ctypes.POINTER(_Instance), u32, ctypes.POINTER(vp),
+                                       ctypes.POINTER(u32)]),
+            "dcs_batch_run": (i32, [vp, vp, i32, vp]),
+            "dcs_batch_destroy": (i32, [vp]),
+            "dcs_batch_total": (u64, [vp]),
+            "dcs_synchronize": (i32, [vp]),
+            "dcs_status_string": (ctypes.c_char_p, [i32]),
+            "dcs_profile_enable": (i32, [i32]),
+            "dcs_profile_read": (i32, [i32, ctypes.POINTER(dbl), ctypes.POINTER(u64)]),
+            "dcs_debug_primitive": (i32, [i32, vp, vp, vp, u64, u64, u64, u64, u64, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != DCS_OK:
+        raise DcsError(rc, what)
+
+
+def _params(n0, dense_ratio):
+    if n0 is None and dense_ratio is None:
+        return None
+    return ctypes.byref(_Params(ctypes.sizeof(_Params), n0 or 0, dense_ratio or 0, 0))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _out_tensor(out, n: int):
+    import torch
+    if out is None:
+        return torch.empty(max(n, 0), dtype=torch.int64, device="cuda")
+    if out.dtype not in (torch.int64, torch.uint64) or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 CUDA tensor")
+    if out.numel() < n:
+        raise ValueError(f"out holds {out.numel()} elements, {n} needed")
+    return out
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def sample(n: int, N: int, seed: int, out=None, stream=None, n0=None, dense_ratio=None,
+           workspace=None):
+    """n distinct values of 1..N, ascending, into an int64 CUDA tensor."""
+    out = _out_tensor(out, n)
+    ws, wsb = (_ptr(workspace), workspace.numel() * workspace.element_size()) \
+        if workspace is not None else (ctypes.c_void_p(0), 0)
+    rc = lib().dcs_sample_ex(n, N, seed, _params(n0, dense_ratio), _ptr(out), ws, wsb,
+                             _stream_handle(stream))
+    _check(rc, "dcs_sample_ex")
+    return out
+
+
+def sample_replacement(n: int, N: int, seed: int, out=None, stream=None, n0=None,
+                       workspace=None):
+    """n independent uniform values of 1..N, sorted, repeats kept."""
+    out = _out_tensor(out, n)
+    ws, wsb = (_ptr(workspace), workspace.numel() * workspace.element_size()) \
+        if workspace is not None else (ctypes.c_void_p(0), 0)
+    rc = lib().dcs_sample_replacement_ex(n, N, seed, _params(n0, None), _ptr(out), ws, wsb,
+                                         _stream_handle(stream))
+    _check(rc, "dcs_sample_replacement_ex")
+    return out
+
+
+def bernoulli_capacity_hint(p: float, N: int) -> int:
+    return int(lib().dcs_bernoulli_capacity_hint(float(p), N))
+
+
+def sample_bernoulli(p: float, N: int, seed: int, out=None, capacity=None, count=None,
+                     stream=None, n0=None):
+    """Bernoulli(p) sample of 1..N.  Returns (out, count) tensors; count is a
+    1-element int64 CUDA tensor with the true number of hits."""
+    import torch
+    if capacity is None:
+        capacity = out.numel() if out is not None else bernoulli_capacity_hint(p, N)
+    out = _out_tensor(out, capacity)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc = lib().dcs_sample_bernoulli_ex(float(p), N, seed, _params(n0, None), _ptr(out), capacity,
+                                       _ptr(count), ctypes.c_void_p(0), 0, _stream_handle(stream))
+    _check(rc, "dcs_sample_bernoulli_ex")
+    return out, count
+
+
+def synchronize(stream=None) -> None:
+    """Wait for the stream; raise DcsError if a kernel latched an error."""
+    _check(lib().dcs_synchronize(_stream_handle(stream)), "dcs_synchronize")
+
+
+def workspace_size(variant: int, n: int, N: int, p: float = 0.0, n0=None, dense_ratio=None) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().dcs_workspace_size(variant, n, N, float(p), _params(n0, dense_ratio),
+                                    ctypes.byref(b)), "dcs_workspace_size")
+    return int(b.value)
+
+
+@dataclass
+class InstanceSpec:
+    n: int
+    N: int
+    seed: int
+    out_offset: int
+    variant: int = 0
+    n0: int = 0
+    dense_ratio: int = 0
+
+
+class Batch:
+    """Many independent instances sampled by one launch sequence."""
+
+    def __init__(self, instances):
+        arr = (_Instance * len(instances))()
+        for i, s in enumerate(instances):
+            arr[i] = _Instance(s.n, s.N, s.seed, s.out_offset, s.variant, s.n0, s.dense_ratio, 0)
+        h = ctypes.c_void_p(0)
+        bad = ctypes.c_uint32(0)
+        rc = lib().dcs_batch_create(arr, len(instances), ctypes.byref(h), ctypes.byref(bad))
+        if rc != DCS_OK:
+            raise DcsError(rc, f"dcs_batch_create (instance {bad.value})")
+        self._h = h
+        self.total = int(lib().dcs_batch_total(h))
+
+    def run(self, out, use_graph: bool = False, stream=None) -> None:
+        _check(lib().dcs_batch_run(self._h, _ptr(out), 1 if use_graph else 0,
+                                   _stream_handle(stream)), "dcs_batch_run")
+
+    def close(self) -> None:
+        if self._h:
+            lib().dcs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().dcs_profile_enable(1 if on else 0), "dcs_profile_enable")
+
+
+def profile_read(kind: int):
+    """(total milliseconds, launches) of kernel kind 0 reset, 1 tree, 2 leaf,
+    3 Bernoulli, accumulated since profile_enable (read after synchronize)."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_uint64(0)
+    _check(lib().dcs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dcs_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def debug_primitive(op: int, x, x2, y, p0=0, p1=0, p2=0, p3=0, stream=None) -> None:
+    count = y.numel() if op != 8 else y.numel() // 4
+    rc = lib().dcs_debug_primitive(op, _ptr(x), _ptr(x2), _ptr(y), count, p0, p1, p2, p3,
+                                   _stream_handle(stream))
+    _check(rc, "dcs_debug_primitive")

@@ -1,0 +1,644 @@
+// dcs_api.hip -- host runtime behind include/dcs.h: argument checks, the
+// per-call plan (Algorithm P cut depth, DFS stack bound, leaf capacity),
+// workspace management, kernel launches, batching with hipGraph replay,
+// kernel timing and latched device errors.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <set>
+#include <vector>
+
+#include "../../include/dcs.h"
+#include "dcs_kernels.hpp"
+
+namespace {
+
+using dcs::Control;
+using dcs::Instance;
+using dcs::Leaf;
+using dcs::Node;
+
+constexpr uint32_t kDefaultN0 = 4096;
+constexpr uint32_t kDefaultDenseRatio = 16;
+constexpr uint32_t kMaxCut = 18;
+constexpr size_t kAlign = 256;
+// A leaf's range must fit a 32-bit draw (the tree splits larger ranges).
+constexpr uint64_t kLeafRange = 1ull << 32;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint32_t floor_log2(uint64_t x) { return x == 0 ? 0 : 63u - static_cast<uint32_t>(__builtin_clzll(x)); }
+
+uint64_t ceil_div_pow2(uint64_t N, uint32_t d) {
+  if (d >= 64) return N ? 1 : 0;
+  const uint64_t m = (1ull << d) - 1;
+  return (N >> d) + ((N & m) ? 1 : 0);
+}
+
+struct Params {
+  uint32_t n0, dense_ratio;
+};
+
+int32_t read_params(const dcs_params* p, Params* out) {
+  out->n0 = kDefaultN0;
+  out->dense_ratio = kDefaultDenseRatio;
+  if (p == nullptr) return DCS_OK;
+  if (p->struct_size != sizeof(dcs_params)) return DCS_EINVAL;
+  if (p->n0 != 0) out->n0 = p->n0;
+  if (p->dense_ratio != 0) out->dense_ratio = p->dense_ratio;
+  if (out->n0 < 2 || out->n0 > dcs::kMaxN0) return DCS_EINVAL;
+  if (out->dense_ratio < 2 || out->dense_ratio > 64) return DCS_EINVAL;
+  return DCS_OK;
+}
+
+// Per-instance plan.
+struct Plan {
+  uint32_t cut = 0;
+  uint64_t threads = 0;
+  uint32_t stack_depth = 1;
+  uint64_t leaf_cap = 0;
+};
+
+// variant 0: without replacement, 1: with replacement.
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
+  Plan pl;
+  if (n == 0) return pl;
+  // Algorithm P cut: depth-`cut` subtrees hold about 2*n0 samples.
+  uint32_t cut = 0;
+  if (n >= 4ull * n0) cut = floor_log2(n / (2ull * n0));
+  // Leaves need N_v <= 2^32: every node above that depth is internal.
+  uint32_t forced = 0;
+  while (ceil_div_pow2(N, forced) > kLeafRange) ++forced;
+  const uint32_t by_count = floor_log2(n) + 1;
+  cut = std::max(cut, std::min(forced, by_count));
+  cut = std::min(cut, kMaxCut);
+  pl.cut = cut;
+  pl.threads = 1ull << cut;
+  // Deepest possible internal node: its range must reach n0 (without
+  // replacement: n_v <= N_v) or 2 (with replacement), or exceed 2^32.
+  const uint64_t need_range = variant == 0 ? std::min<uint64_t>(n0, kLeafRange + 1) : 2;
+  uint32_t d_int = 0;
+  while (d_int < 63 && ceil_div_pow2(N, d_int + 1) >= need_range) ++d_int;
+  pl.stack_depth = (d_int + 2 > cut) ? d_int + 2 - cut : 2;
+  // Leaf capacity: the tree has about 1.5 n/n0 leaves (at most n/n0 internal
+  // nodes per level, halving sizes); range-forced levels add at most
+  // min(n, 2^(forced+1)) small leaves; constant pieces of N_v = 1 leaves.
+  uint64_t cap = 4 * ((n + n0 - 1) / n0) + 64;
+  cap += std::min<uint64_t>(n, forced >= 62 ? n : (2ull << forced));
+  if (variant == 1) cap += n / dcs::kFillPiece + std::min<uint64_t>(N, 4 * (n / n0) + 4) + 2;
+  pl.leaf_cap = cap;
+  return pl;
+}
+
+// Workspace layout for a tree launch.
+struct TreeLayout {
+  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, total = 0;
+};
+
+TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth) {
+  TreeLayout L;
+  size_t o = 0;
+  L.ctl = o;
+  o = align_up(o + sizeof(Control));
+  L.inst = o;
+  o = align_up(o + sizeof(Instance) * std::max<uint32_t>(n_inst, 1));
+  L.leaves = o;
+  o = align_up(o + sizeof(Leaf) * leaf_cap);
+  L.stacks = o;
+  o = align_up(o + sizeof(Node) * threads * stack_depth);
+  L.total = o;
+  return L;
+}
+
+struct BernPlan {
+  uint64_t chunk = 0, n_chunks = 0;
+  int fp32 = 1;
+  double c64 = 0;
+  float c32 = 0;
+};
+
+double host_log1p_series(double x);
+
+// Chunk length 2^floor(log2(n0/p)) clamped to [2^12, 2^32].
+uint64_t bern_chunk_len(double p, uint32_t n0) {
+  const double x = static_cast<double>(n0) / p;
+  if (!(x < 4294967296.0)) return 1ull << 32;
+  int e;
+  frexp(x, &e);
+  int lg = e - 1;
+  lg = std::max(lg, 12);
+  lg = std::min(lg, 32);
+  return 1ull << lg;
+}
+
+// ---- host copies of the library's double-precision log (for the Bernoulli
+// constant c = 1/ln(1-p), computed once per call on the host) ---------------
+constexpr double kLn2HiH = 0x1.62e42feep-1;
+constexpr double kLn2LoH = 0x1.a39ef35793c76p-33;
+constexpr double kSqrt2H = 0x1.6a09e667f3bcdp+0;
+
+double host_atanh2(double f) {
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double p = 1.0 / 23.0;
+  p = 1.0 / 21.0 + z * p;
+  p = 1.0 / 19.0 + z * p;
+  p = 1.0 / 17.0 + z * p;
+  p = 1.0 / 15.0 + z * p;
+  p = 1.0 / 13.0 + z * p;
+  p = 1.0 / 11.0 + z * p;
+  p = 1.0 / 9.0 + z * p;
+  p = 1.0 / 7.0 + z * p;
+  p = 1.0 / 5.0 + z * p;
+  p = 1.0 / 3.0 + z * p;
+  const double t = s + s;
+  return t + t * (z * p);
+}
+
+double host_log(double x) {
+  uint64_t b;
+  memcpy(&b, &x, 8);
+  int e = static_cast<int>((b >> 52) & 0x7FF) - 1023;
+  const uint64_t mb = (b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+  double m;
+  memcpy(&m, &mb, 8);
+  if (m >= kSqrt2H) {
+    m = m * 0.5;
+    e += 1;
+  }
+  const double r = host_atanh2(m - 1.0);
+  const double de = static_cast<double>(e);
+  return de * kLn2HiH + (de * kLn2LoH + r);
+}
+
+double host_log1p_series(double x) {
+  if (x > -0.25 && x < 0.25) return host_atanh2(x);
+  return host_log(1.0 + x);
+}
+
+// ---- device context -------------------------------------------------------
+struct Timing {
+  int kind;
+  hipEvent_t a, b;
+};
+
+struct DeviceCtx {
+  bool init = false;
+  int cus = 256;
+  int leaf_occupancy = 2;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+std::mutex g_mu;
+std::vector<DeviceCtx> g_dev;
+std::set<void*> g_ctl_used;  // control blocks to check at synchronize
+bool g_profile = false;
+std::vector<Timing> g_timings;
+double g_prof_ms[4] = {0, 0, 0, 0};
+uint64_t g_prof_n[4] = {0, 0, 0, 0};
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? DCS_OK : DCS_EHIP; }
+
+int32_t device_ctx(DeviceCtx** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DCS_EHIP;
+  if (static_cast<int>(g_dev.size()) <= dev) g_dev.resize(dev + 1);
+  DeviceCtx& c = g_dev[dev];
+  if (!c.init) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DCS_EHIP;
+    c.cus = prop.multiProcessorCount;
+    c.leaf_occupancy = dcs::leaf_occupancy();
+    c.init = true;
+  }
+  *out = &c;
+  return DCS_OK;
+}
+
+// Library-owned workspace of at least `bytes` (grown on demand).
+int32_t own_workspace(DeviceCtx* c, size_t bytes, void** ws) {
+  if (c->ws_bytes < bytes) {
+    if (c->ws) {
+      if (hipDeviceSynchronize() != hipSuccess) return DCS_EHIP;
+      g_ctl_used.erase(c->ws);
+      if (hipFree(c->ws) != hipSuccess) return DCS_EHIP;
+      c->ws = nullptr;
+      c->ws_bytes = 0;
+    }
+    size_t grow = std::max(bytes, static_cast<size_t>(64) << 20);
+    if (hipMalloc(&c->ws, grow) != hipSuccess) return DCS_ENOMEM;
+    if (hipMemset(c->ws, 0, sizeof(Control)) != hipSuccess) return DCS_EHIP;
+    c->ws_bytes = grow;
+  }
+  *ws = c->ws;
+  return DCS_OK;
+}
+
+void timing_begin(int kind, hipStream_t s, Timing* t) {
+  if (!g_profile) return;
+  t->kind = kind;
+  (void)hipEventCreate(&t->a);
+  (void)hipEventCreate(&t->b);
+  (void)hipEventRecord(t->a, s);
+}
+
+void timing_end(hipStream_t s, Timing* t) {
+  if (!g_profile) return;
+  (void)hipEventRecord(t->b, s);
+  g_timings.push_back(*t);
+}
+
+// Enqueue reset + tree + leaf for the instances already in the workspace.
+int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
+                          uint32_t n_inst, uint64_t threads, uint64_t leaf_cap,
+                          uint32_t stack_depth, uint64_t* out, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
+  Instance* inst = reinterpret_cast<Instance*>(base + L.inst);
+  Leaf* leaves = reinterpret_cast<Leaf*>(base + L.leaves);
+  Node* stacks = reinterpret_cast<Node*>(base + L.stacks);
+  Timing t0{}, t1{}, t2{};
+  timing_begin(0, s, &t0);
+  hipError_t e = dcs::launch_reset(ctl, single, inst, s);
+  timing_end(s, &t0);
+  if (e != hipSuccess) return DCS_EHIP;
+  timing_begin(1, s, &t1);
+  e = dcs::launch_tree(inst, n_inst, threads, leaves, leaf_cap, stacks, stack_depth, ctl, s);
+  timing_end(s, &t1);
+  if (e != hipSuccess) return DCS_EHIP;
+  const uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(leaf_cap, static_cast<uint64_t>(c->cus) * c->leaf_occupancy));
+  timing_begin(2, s, &t2);
+  e = dcs::launch_leaf(inst, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+  timing_end(s, &t2);
+  if (e != hipSuccess) return DCS_EHIP;
+  g_ctl_used.insert(ctl);
+  return DCS_OK;
+}
+
+int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                    uint64_t* out, void* workspace, size_t ws_bytes, void* stream) {
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (variant == 0 && n > N) return DCS_EINVAL;
+  if (variant == 1 && N == 0 && n > 0) return DCS_EINVAL;
+  if (n > 0 && out == nullptr) return DCS_EINVAL;
+  if (n == 0) return DCS_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  const Plan pl = make_plan(n, N, P.n0, variant);
+  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth);
+  void* ws = workspace;
+  if (ws == nullptr) {
+    rc = own_workspace(c, L.total, &ws);
+    if (rc) return rc;
+  } else if (ws_bytes < L.total) {
+    return DCS_ENOMEM;
+  }
+  Instance I{};
+  I.n = n;
+  I.N = N;
+  I.seed = seed;
+  I.out_offset = 0;
+  I.thread_base = 0;
+  I.n0 = P.n0;
+  I.dense_ratio = P.dense_ratio;
+  I.variant = variant;
+  I.cut = pl.cut;
+  return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.leaf_cap, pl.stack_depth, out,
+                           static_cast<hipStream_t>(stream));
+}
+
+struct BernLayout {
+  size_t ctl = 0, status = 0, total = 0;
+};
+
+BernLayout bern_layout(uint64_t n_chunks) {
+  BernLayout L;
+  size_t o = 0;
+  L.ctl = o;
+  o = align_up(o + sizeof(Control));
+  L.status = o;
+  o = align_up(o + sizeof(unsigned long long) * n_chunks);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dcs_sample(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev, void* stream) {
+  return sample_tree(0, n, N, seed, nullptr, out_dev, nullptr, 0, stream);
+}
+
+int32_t dcs_sample_ex(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                      uint64_t* out_dev, void* workspace, size_t ws_bytes, void* stream) {
+  return sample_tree(0, n, N, seed, params, out_dev, workspace, ws_bytes, stream);
+}
+
+int32_t dcs_sample_replacement(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev,
+                               void* stream) {
+  return sample_tree(1, n, N, seed, nullptr, out_dev, nullptr, 0, stream);
+}
+
+int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                                  uint64_t* out_dev, void* workspace, size_t ws_bytes,
+                                  void* stream) {
+  return sample_tree(1, n, N, seed, params, out_dev, workspace, ws_bytes, stream);
+}
+
+uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N) {
+  if (!(p >= 0.0 && p <= 1.0)) return 0;
+  const double m = static_cast<double>(N) * p;
+  const double v = m * (1.0 - p);
+  double cap = m + 10.0 * sqrt(v) + 64.0;
+  if (cap > static_cast<double>(N)) cap = static_cast<double>(N);
+  return static_cast<uint64_t>(cap);
+}
+
+int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_params* params,
+                                uint64_t* out_dev, uint64_t capacity, uint64_t* count_dev,
+                                void* workspace, size_t ws_bytes, void* stream) {
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (!(p >= 0.0 && p <= 1.0) || N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (count_dev == nullptr || (capacity > 0 && out_dev == nullptr)) return DCS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  if (p == 0.0 || N == 0) {
+    return hip_status(hipMemsetAsync(count_dev, 0, sizeof(uint64_t), s));
+  }
+  if (p == 1.0) return hip_status(dcs::launch_bernoulli_fill(N, out_dev, capacity, count_dev, s));
+  const uint64_t chunk = bern_chunk_len(p, P.n0);
+  const uint64_t n_chunks = (N + chunk - 1) / chunk;
+  const BernLayout L = bern_layout(n_chunks);
+  void* ws = workspace;
+  if (ws == nullptr) {
+    rc = own_workspace(c, L.total, &ws);
+    if (rc) return rc;
+  } else if (ws_bytes < L.total) {
+    return DCS_ENOMEM;
+  }
+  char* base = static_cast<char*>(ws);
+  Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(base + L.status);
+  const double c64 = 1.0 / host_log1p_series(-p);
+  const float c32 = static_cast<float>(c64);
+  const int fp32 = p >= 0x1p-10 ? 1 : 0;
+  Timing t0{}, t1{};
+  timing_begin(0, s, &t0);
+  hipError_t e = dcs::launch_zero(ctl, status, n_chunks, s);
+  timing_end(s, &t0);
+  if (e != hipSuccess) return DCS_EHIP;
+  const uint32_t grid = static_cast<uint32_t>(
+      std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->leaf_occupancy)));
+  const uint32_t lds_cap = 2 * P.n0 + 64;
+  timing_begin(3, s, &t1);
+  e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,
+                            count_dev, ctl, grid, lds_cap, s);
+  timing_end(s, &t1);
+  if (e != hipSuccess) return DCS_EHIP;
+  g_ctl_used.insert(ctl);
+  return DCS_OK;
+}
+
+int32_t dcs_sample_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t* out_dev,
+                             uint64_t capacity, uint64_t* count_dev, void* stream) {
+  return dcs_sample_bernoulli_ex(p, N, seed, nullptr, out_dev, capacity, count_dev, nullptr, 0,
+                                 stream);
+}
+
+int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for_bernoulli,
+                           const dcs_params* params, size_t* bytes) {
+  Params P;
+  if (bytes == nullptr || read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (variant == 0 || variant == 1) {
+    if (variant == 0 && n > N) return DCS_EINVAL;
+    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant));
+    *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth).total;
+    return DCS_OK;
+  }
+  if (variant == 2) {
+    const double p = p_for_bernoulli;
+    if (!(p >= 0.0 && p <= 1.0)) return DCS_EINVAL;
+    if (p == 0.0 || p == 1.0 || N == 0) {
+      *bytes = align_up(sizeof(Control));
+      return DCS_OK;
+    }
+    const uint64_t chunk = bern_chunk_len(p, P.n0);
+    *bytes = bern_layout((N + chunk - 1) / chunk).total;
+    return DCS_OK;
+  }
+  return DCS_EINVAL;
+}
+
+// ---- batch ----------------------------------------------------------------
+}  // extern "C"
+
+struct dcs_batch {
+  std::vector<Instance> host;
+  uint64_t threads = 0, leaf_cap = 0, total_out = 0;
+  uint32_t stack_depth = 1;
+  TreeLayout layout;
+  void* ws = nullptr;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t* graph_out = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+extern "C" {
+
+int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batch** batch,
+                         uint32_t* bad_index) {
+  if (batch == nullptr || (count > 0 && instances == nullptr) || count == 0) return DCS_EINVAL;
+  *batch = nullptr;
+  auto* b = new dcs_batch();
+  uint64_t tb = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const dcs_instance& d = instances[i];
+    dcs_params pp{sizeof(dcs_params), d.n0, d.dense_ratio, 0};
+    Params P;
+    const bool ok = read_params(&pp, &P) == DCS_OK && d.N <= DCS_MAX_UNIVERSE && d.variant <= 1 &&
+                    !(d.variant == 0 && d.n > d.N) && !(d.variant == 1 && d.N == 0 && d.n > 0);
+    if (!ok) {
+      if (bad_index) *bad_index = i;
+      delete b;
+      return DCS_EINVAL;
+    }
+    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant);
+    Instance I{};
+    I.n = d.n;
+    I.N = d.N;
+    I.seed = d.seed;
+    I.out_offset = d.out_offset;
+    I.thread_base = tb;
+    I.n0 = P.n0;
+    I.dense_ratio = P.dense_ratio;
+    I.variant = d.variant;
+    I.cut = pl.cut;
+    tb += pl.threads;
+    b->leaf_cap += pl.leaf_cap;
+    b->stack_depth = std::max(b->stack_depth, pl.stack_depth);
+    b->total_out += d.n;
+    b->host.push_back(I);
+  }
+  b->threads = tb;
+  b->layout = tree_layout(count, b->leaf_cap, b->threads, b->stack_depth);
+  if (hipGetDevice(&b->device) != hipSuccess || hipMalloc(&b->ws, b->layout.total) != hipSuccess) {
+    delete b;
+    return DCS_ENOMEM;
+  }
+  char* base = static_cast<char*>(b->ws);
+  if (hipMemset(base + b->layout.ctl, 0, sizeof(Control)) != hipSuccess ||
+      hipMemcpy(base + b->layout.inst, b->host.data(), sizeof(Instance) * count,
+                hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(b->ws);
+    delete b;
+    return DCS_EHIP;
+  }
+  *batch = b;
+  return DCS_OK;
+}
+
+uint64_t dcs_batch_total(const dcs_batch* batch) { return batch ? batch->total_out : 0; }
+
+int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* stream) {
+  if (b == nullptr || out_dev == nullptr) return DCS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  const uint32_t n_inst = static_cast<uint32_t>(b->host.size());
+  if (!use_graph || g_profile) {
+    return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
+                             b->stack_depth, out_dev, s);
+  }
+  if (s == nullptr) return DCS_EINVAL;  // capture needs a real stream
+  if (b->exec == nullptr || b->graph_out != out_dev) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      (void)hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DCS_EHIP;
+    rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
+                           b->stack_depth, out_dev, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != DCS_OK) return rc;
+    if (e != hipSuccess) return DCS_EHIP;
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return DCS_EHIP;
+    b->graph_out = out_dev;
+  }
+  return hip_status(hipGraphLaunch(b->exec, s));
+}
+
+int32_t dcs_batch_destroy(dcs_batch* b) {
+  if (b == nullptr) return DCS_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  char* base = static_cast<char*>(b->ws);
+  g_ctl_used.erase(base + b->layout.ctl);
+  if (b->ws) (void)hipFree(b->ws);
+  delete b;
+  return DCS_OK;
+}
+
+// ---- status, timing, diagnostics -------------------------------------------
+int32_t dcs_synchronize(void* stream) {
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DCS_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  unsigned int any = 0;
+  for (void* p : g_ctl_used) {
+    Control* ctl = static_cast<Control*>(p);
+    unsigned int err = 0;
+    if (hipMemcpy(&err, &ctl->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return DCS_EHIP;
+    if (err) {
+      any |= err;
+      const unsigned int zero = 0;
+      if (hipMemcpy(&ctl->error, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return DCS_EHIP;
+    }
+  }
+  if (g_profile) {
+    for (Timing& t : g_timings) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+        g_prof_ms[t.kind] += ms;
+        g_prof_n[t.kind] += 1;
+      }
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    g_timings.clear();
+  }
+  return any ? DCS_EDEVICE : DCS_OK;
+}
+
+const char* dcs_status_string(int32_t st) {
+  switch (st) {
+    case DCS_OK: return "ok";
+    case DCS_EINVAL: return "invalid argument";
+    case DCS_ENOMEM: return "workspace too small or device allocation failed";
+    case DCS_EHIP: return "HIP runtime error";
+    case DCS_EOVERFLOW: return "Bernoulli count exceeds capacity";
+    case DCS_EDEVICE: return "a kernel latched an error (capacity bound exceeded)";
+    case DCS_ENOTSUP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+int32_t dcs_profile_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Timing& t : g_timings) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_timings.clear();
+  for (int i = 0; i < 4; ++i) {
+    g_prof_ms[i] = 0;
+    g_prof_n[i] = 0;
+  }
+  g_profile = enable != 0;
+  return DCS_OK;
+}
+
+int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches) {
+  if (kind < 0 || kind > 3 || total_ms == nullptr || launches == nullptr) return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *total_ms = g_prof_ms[kind];
+  *launches = g_prof_n[kind];
+  return DCS_OK;
+}
+
+int32_t dcs_debug_primitive(int32_t op, const void* x_dev, const void* x2_dev, void* y_dev,
+                            uint64_t count, uint64_t p0, uint64_t p1, uint64_t p2, uint64_t p3,
+                            void* stream) {
+  if (op < 0 || op > 9 || (count > 0 && (x_dev == nullptr || y_dev == nullptr))) return DCS_EINVAL;
+  if ((op == 4 || op == 5) && count > 0 && x2_dev == nullptr) return DCS_EINVAL;
+  return hip_status(dcs::launch_debug(op, x_dev, x2_dev, y_dev, count, p0, p1, p2, p3,
+                                      static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// dcs_kernels.hpp -- device data layout and kernel launch helpers shared by
+// the kernels and the host runtime of the sampler library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dcs {
+
+// One instance of the sampling problem (single call: one entry; batch: many).
+struct Instance {
+  uint64_t n;           // sample size (without / with replacement)
+  uint64_t N;           // universe 1..N
+  uint64_t seed;
+  uint64_t out_offset;  // first output element of this instance
+  uint64_t thread_base; // first tree-kernel thread of this instance
+  uint32_t n0;
+  uint32_t dense_ratio;
+  uint32_t variant;     // 0 without replacement, 1 with replacement
+  uint32_t cut;         // Algorithm P depth: 2^cut tree threads
+};
+
+// A recursion-tree node (Fig. 1): node id (root 1, children 2i, 2i+1), the
+// range lo+1 .. lo+Nv, the sample count nv and the output offset off of its
+// part of the (sorted) sample.
+struct Node {
+  uint64_t id, lo, Nv, nv, off;
+};
+
+// A leaf job for the leaf kernel: a node plus the instance it belongs to.
+struct Leaf {
+  uint64_t id, lo, Nv, nv, off;
+  uint32_t inst;
+  uint32_t pad;
+};
+
+// Control block at the start of a workspace.
+struct Control {
+  unsigned long long leaf_count;   // leaves appended by the tree kernel
+  unsigned long long leaf_ticket;  // next leaf to hand out in the leaf kernel
+  unsigned long long chunk_ticket; // Bernoulli: next chunk to hand out
+  unsigned int error;              // latched error bits (kErr*)
+  unsigned int pad;
+  unsigned long long bern_count;   // Bernoulli: total hits (copied to the caller)
+};
+
+constexpr unsigned kErrLeafCapacity = 1u;   // more leaves than the workspace holds
+constexpr unsigned kErrStackDepth = 2u;     // tree deeper than the planned stack
+constexpr unsigned kErrSpinLimit = 4u;      // Bernoulli look-back waited too long
+constexpr unsigned kErrLeafTooLarge = 8u;   // a leaf exceeds the kernel's LDS bound
+
+constexpr int kLeafBlock = 256;             // threads of a leaf work-group
+constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
+constexpr uint64_t kFillPiece = 1ull << 16; // constant-fill leaves are cut to this
+
+// Kernel launchers (defined in dcs_kernels.hip).
+// Zero the counters of a control block (the error word is kept: it is
+// sticky until the host reads and clears it); if `single` is non-null, also
+// store that instance as entry 0 of the instance table.
+hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, hipStream_t stream);
+// launch_reset for a Bernoulli call plus zeroing of its look-back status words.
+hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream);
+// Resident leaf work-groups per compute unit.
+int leaf_occupancy();
+hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
+                       Leaf* leaves, uint64_t leaf_cap, Node* stacks, uint32_t stack_depth,
+                       Control* ctl, hipStream_t stream);
+hipError_t launch_leaf(const Instance* inst, const Leaf* leaves, uint64_t leaf_cap,
+                       uint64_t* out, Control* ctl, uint32_t grid, hipStream_t stream);
+hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
+                            uint64_t n_chunks, int fp32, double c64, float c32,
+                            unsigned long long* status, uint64_t* out, uint64_t capacity,
+                            uint64_t* count_dev, Control* ctl, uint32_t grid,
+                            uint32_t lds_cap, hipStream_t stream);
+hipError_t launch_bernoulli_fill(uint64_t N, uint64_t* out, uint64_t capacity,
+                                 uint64_t* count_dev, hipStream_t stream);
+hipError_t launch_debug(int op, const void* x, const void* x2, void* y, uint64_t count,
+                        uint64_t p0, uint64_t p1, uint64_t p2, uint64_t p3, hipStream_t stream);
+
+}  // namespace dcs

@@ -1,0 +1,138 @@
+"""Bit-exact parity of the HIP sampler with the oracle (GPU), through the C ABI.
+
+Full outputs are compared element by element at sizes the oracle finishes in
+seconds (several leaves, ragged tails, every leaf kind); the 8 GiB
+configuration is compared on windows the oracle computes on its own, plus
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import announce, dcs, first_mismatch, to_np_u64
+
+pytestmark = pytest.mark.gpu
+
+# (n, N, seed, n0, dense_ratio)
+WOR_CASES = [
+    (1 << 20, 1 << 32, 1, 4096, 16),          # configuration 1 (n = 2^20 of 2^32)
+    (0, 10, 1, 4096, 16),                     # empty sample
+    (1, 1, 3, 4096, 16),
+    (10, 10, 3, 4, 16),                       # n = N, tiny leaves
+    (5000, 5000, 2, 4096, 16),                # n = N, dense leaves with rho = 1
+    (4095, 2**32, 5, 4096, 16),               # one sparse leaf, full 32-bit range
+    (4095, 2**32 + 1, 5, 4096, 16),           # one split forced by the 2^32 range rule
+    (300, 5000, 9, 4096, 2),                  # one sparse leaf with many duplicates
+    (200, 2**31 + 1, 9, 4096, 2),             # half of all words void
+    (1 << 16, (1 << 16) + 3, 4, 4096, 16),    # nearly full: dense leaves
+    (1 << 20, 1 << 21, 7, 4096, 16),          # density 0.5 (configuration 2b, scaled)
+    (123457, 10**9 + 7, 11, 4096, 16),        # ragged sizes everywhere
+    (100000, 2**40 + 3, 12, 512, 16),         # range-forced depth, small n0
+    (77777, 300000, 13, 64, 16),              # dense leaves, small n0 (many leaves)
+    (50000, 2**44, 14, 4096, 16),             # very sparse
+    (200, 2**52, 15, 4096, 16),               # largest universe
+    (3, 2**52, 16, 2, 16),                    # n0 = 2, depth 50
+    (20000, 640000, 17, 4096, 16),            # density 1/32: sparse, duplicates common
+]
+
+
+@pytest.mark.parametrize("n,N,seed,n0,dr", WOR_CASES)
+def test_without_replacement_matches_oracle(ref, n, N, seed, n0, dr):
+    import torch
+    m = dcs()
+    announce(f"wor n={n} N={N} seed={seed} n0={n0} dr={dr}")
+    out = m.sample(n, N, seed, n0=n0, dense_ratio=dr)
+    m.synchronize()
+    got = to_np_u64(out)
+    want = ref.sample(n, N, seed, n0=n0, dense_ratio=dr)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_config1_invariants_and_repeatability():
+    import torch
+    m = dcs()
+    n, N = 1 << 20, 1 << 32
+    announce("config 1 repeat")
+    a = m.sample(n, N, 1)
+    b = torch.empty_like(a)
+    m.sample(n, N, 1, out=b)
+    m.synchronize()
+    assert torch.equal(a, b)
+    d = a[1:] - a[:-1]
+    assert bool((d > 0).all())
+    assert int(a[0]) >= 1 and int(a[-1]) <= N
+
+
+WR_CASES = [
+    (1 << 20, 1 << 34, 7, 4096),
+    (7, 1, 3, 4096),                 # N = 1: all ones
+    (1 << 18, 2, 5, 4096),           # constant leaves cut into pieces
+    (100000, 3 * 10**6 + 1, 11, 512),
+    (5, 3, 1, 2),
+    (1 << 16, 1 << 10, 8, 4096),     # many repeats per value
+    (3000, 2**45 + 1, 9, 4096),
+]
+
+
+@pytest.mark.parametrize("n,N,seed,n0", WR_CASES)
+def test_with_replacement_matches_oracle(ref, n, N, seed, n0):
+    m = dcs()
+    announce(f"wr n={n} N={N} seed={seed} n0={n0}")
+    out = m.sample_replacement(n, N, seed, n0=n0)
+    m.synchronize()
+    got = to_np_u64(out)
+    want = ref.replacement(n, N, seed, n0=n0)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+BERN_CASES = [
+    (0.01, 1 << 26, 7),      # p of configuration 3, smaller universe
+    (0.3, 100003, 1),
+    (2.0**-10, 1 << 24, 2),  # smallest single-precision p
+    (1e-4, 1 << 28, 3),      # double-precision skips
+    (0.97, 50000, 4),
+    (0.0, 1000, 5),
+    (1.0, 1000, 6),
+    (0.5, 3, 7),
+]
+
+
+@pytest.mark.parametrize("p,N,seed", BERN_CASES)
+def test_bernoulli_matches_oracle(ref, p, N, seed):
+    m = dcs()
+    announce(f"bernoulli p={p} N={N} seed={seed}")
+    out, cnt = m.sample_bernoulli(p, N, seed)
+    m.synchronize()
+    c = int(cnt.item())
+    want = ref.bernoulli(p, N, seed)
+    assert c == want.size
+    got = to_np_u64(out[:c])
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_bernoulli_capacity_overflow_keeps_prefix(ref):
+    import torch
+    m = dcs()
+    p, N, seed = 0.01, 1 << 24, 9
+    announce("bernoulli overflow")
+    want = ref.bernoulli(p, N, seed)
+    cap = want.size // 2
+    out = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    _, cnt = m.sample_bernoulli(p, N, seed, out=out, capacity=cap)
+    m.synchronize()
+    assert int(cnt.item()) == want.size
+    assert np.array_equal(to_np_u64(out), want[:cap])
+
+
+def test_invalid_arguments_rejected():
+    import torch
+    m = dcs()
+    out = torch.empty(16, dtype=torch.int64, device="cuda")
+    for args in [(11, 10, 1), (1, 2**52 + 1, 1)]:
+        with pytest.raises(m.DcsError):
+            m.sample(*args, out=out)
+    with pytest.raises(m.DcsError):
+        m.sample(4, 10, 1, out=out, n0=1)
+    with pytest.raises(m.DcsError):
+        m.sample_bernoulli(1.5, 10, 1, out=out)
+    with pytest.raises(m.DcsError):
+        m.sample_replacement(3, 0, 1, out=out)
