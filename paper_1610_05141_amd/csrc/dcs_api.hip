@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -65,7 +66,7 @@ struct Plan {
 };
 
 // variant 0: without replacement, 1: with replacement.
-Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias = 0) {
   Plan pl;
   if (n == 0) return pl;
   // Algorithm P cut: depth-`cut` subtrees hold about 2*n0 samples.
@@ -76,6 +77,8 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
   while (ceil_div_pow2(N, forced) > kLeafRange) ++forced;
   const uint32_t by_count = floor_log2(n) + 1;
   cut = std::max(cut, std::min(forced, by_count));
+  const int64_t biased = static_cast<int64_t>(cut) + cut_bias;
+  cut = static_cast<uint32_t>(std::max<int64_t>(0, biased));
   cut = std::min(cut, kMaxCut);
   pl.cut = cut;
   pl.threads = 1ull << cut;
@@ -191,6 +194,10 @@ struct DeviceCtx {
   bool init = false;
   int cus = 256;
   int leaf_occupancy = 2;
+  // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
+  // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut
+  int64_t leaf_grid = 0;
+  int32_t cut_bias = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
 };
@@ -215,6 +222,8 @@ int32_t device_ctx(DeviceCtx** out) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DCS_EHIP;
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
+    if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
+    if (const char* e = getenv("DCS_CUT_BIAS")) c.cut_bias = atoi(e);
     c.init = true;
   }
   *out = &c;
@@ -272,9 +281,11 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   e = dcs::launch_tree(inst, n_inst, threads, leaves, leaf_cap, stacks, stack_depth, ctl, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
-  const uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(leaf_cap, static_cast<uint64_t>(c->cus) * c->leaf_occupancy));
+  uint64_t want = static_cast<uint64_t>(c->cus) * c->leaf_occupancy;
+  if (c->leaf_grid > 0) want = static_cast<uint64_t>(c->leaf_grid);
+  want = std::max<uint64_t>(1, std::min<uint64_t>(want, leaf_cap));
   timing_begin(2, s, &t2);
-  e = dcs::launch_leaf(inst, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+  e = dcs::launch_leaf(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
   g_ctl_used.insert(ctl);
@@ -294,7 +305,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   DeviceCtx* c;
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
-  const Plan pl = make_plan(n, N, P.n0, variant);
+  const Plan pl = make_plan(n, N, P.n0, variant, c->cut_bias);
   const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth);
   void* ws = workspace;
   if (ws == nullptr) {

@@ -64,14 +64,15 @@ __device__ __forceinline__ uint4 philox_block(const Stream& s, uint32_t block) {
   uint32_t k0 = s.k0, k1 = s.k1;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi_a = __umulhi(0xD2511F53u, x0);
-    const uint32_t lo_a = 0xD2511F53u * x0;
-    const uint32_t hi_b = __umulhi(0xCD9E8D57u, x2);
-    const uint32_t lo_b = 0xCD9E8D57u * x2;
-    x0 = hi_b ^ x1 ^ k0;
-    x1 = lo_b;
-    x2 = hi_a ^ x3 ^ k1;
-    x3 = lo_a;
+    // one 32x32->64 multiply-add each (v_mad_u64_u32) gives both halves
+    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * x0;
+    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * x2;
+    const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ x1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ x3 ^ k1;
+    x1 = static_cast<uint32_t>(pb);
+    x3 = static_cast<uint32_t>(pa);
+    x0 = n0;
+    x2 = n2;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -1,13 +1,14 @@
 // dcs_kernels.hip -- the sampler's kernels for gfx950.
 //
-//   k_reset      zero a workspace control block
+//   k_reset      zero a workspace control block (and store a single instance)
 //   k_tree       recursion tree: each thread follows one root-to-depth-`cut`
 //                path of Algorithm R, recomputing the splits on the way
 //                exactly as a processing element of Algorithm P does
 //                (paper Sec. 3.2, Fig. 2), then expands the subtree below by
-//                a depth-first walk; every leaf becomes a job.
-//   k_leaf       persistent work-groups take leaf jobs from an atomic ticket
-//                (the atomic jobs of Sec. 4.2) and run the base case:
+//                a depth-first walk; every leaf becomes a self-contained job.
+//   k_leaf       persistent work-groups, each taking every G-th leaf job (the
+//                atomic jobs of Sec. 4.2, assigned statically so that job
+//                records stream into LDS ahead of use), run the base case:
 //                  sparse  Algorithm H semantics (Sec. 2): the first n_v
 //                          distinct values of the node's stream, found in
 //                          rounds with an LDS counting sort by most
@@ -27,53 +28,27 @@
 namespace dcs {
 
 // ---------------------------------------------------------------------------
-// Small block-wide helpers (kLeafBlock threads = 4 waves of 64).
+// Block-wide exclusive prefix sums (one value per thread).  `scratch` holds
+// BLOCK/64 words of LDS; *total receives the block sum.
 // ---------------------------------------------------------------------------
-constexpr int kWaves = kLeafBlock / 64;
-
-// Exclusive prefix sum over the block of one value per thread; *total gets
-// the block sum.  `scratch` holds kWaves words of LDS.
-__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* scratch,
-                                                    uint32_t* total) {
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
+  constexpr int kW = BLOCK / 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  uint32_t x = v;
+  T x = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
+    const T y = __shfl_up(x, d, 64);
     if (lane >= d) x += y;
   }
   if (lane == 63) scratch[wave] = x;
   __syncthreads();
-  uint32_t before = 0, all = 0;
+  T before = 0, all = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const uint32_t s = scratch[w];
-    before += (w < wave) ? s : 0u;
-    all += s;
-  }
-  __syncthreads();
-  *total = all;
-  return before + x - v;
-}
-
-__device__ __forceinline__ uint64_t block_scan_excl64(uint64_t v, uint64_t* scratch,
-                                                      uint64_t* total) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  uint64_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) scratch[wave] = x;
-  __syncthreads();
-  uint64_t before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const uint64_t s = scratch[w];
-    before += (w < wave) ? s : 0ull;
+  for (int w = 0; w < kW; ++w) {
+    const T s = scratch[w];
+    before += (w < wave) ? s : T(0);
     all += s;
   }
   __syncthreads();
@@ -85,205 +60,49 @@ __device__ __forceinline__ uint32_t bit_length(uint64_t x) {
   return x == 0 ? 0u : 64u - static_cast<uint32_t>(__clzll(static_cast<long long>(x)));
 }
 
-// ---------------------------------------------------------------------------
-// LDS layout of a leaf work-group (32-bit words).
-//   [0, kRegionA)           sparse: keys | tmp      dense: positions
-//   [kRegionA, +kRegionB)   sparse: bucket counts   dense: kept values
-//   then mask words and a little scratch.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kKeys = kMaxN0;                   // 4096 keys
-constexpr uint32_t kDenseCap = 2 * kMaxN0 + 64;       // largest accepted n'
-constexpr uint32_t kRegionA = 2 * kMaxN0 + 128;       // >= kDenseCap + 1
-constexpr uint32_t kRegionB = kMaxN0;                 // buckets / kept values
-constexpr uint32_t kMaskWords = (kDenseCap + 32) / 32 + 1;
-constexpr uint32_t kSmemWords = kRegionA + kRegionB + kMaskWords + 32;
-
-struct LeafSmem {
-  uint32_t* keys;   // kKeys
-  uint32_t* tmp;    // kKeys
-  uint32_t* buck;   // kRegionB
-  uint32_t* mask;   // kMaskWords
-  uint32_t* scr;    // 32 words of scratch
-};
-
-// ---------------------------------------------------------------------------
-// The first `need` non-void values of a 32-bit stream in [0, s), starting at
-// word t0, delivered in stream order to sink(p, value) for p = 0..need-1.
-// Returns the word index just after the last value taken.  Only as many
-// words as could still be needed are generated (no voids assumed); a void
-// costs one more round.
-// ---------------------------------------------------------------------------
-template <class Sink>
-__device__ uint64_t take_values(const Stream& st, uint64_t t0, uint32_t need, uint64_t s,
-                                uint32_t thr, bool pow2, uint32_t pshift, uint32_t* scr,
-                                Sink sink) {
-  if (need == 0) return t0;
-  uint32_t done = 0;
-  uint64_t t = t0;  // next word to examine
-  uint64_t next = t0;
-  while (done < need) {
-    const uint32_t want = need - done;
-    const uint64_t first_blk = t >> 2;
-    // words [t, last_word) are examined this round: at most the blocks the
-    // work-group covers, and no more words than values still wanted
-    uint64_t last_word = t + want;
-    const uint64_t reach = (first_blk + kLeafBlock) << 2;
-    if (last_word > reach) last_word = reach;
-    const uint64_t blk = first_blk + threadIdx.x;
-    uint32_t v[4];
-    uint32_t ok = 0;  // bit j: word j of this block is a value in range
-    if ((blk << 2) < last_word) {
-      const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint64_t tj = (blk << 2) + j;
-        const uint32_t word = pick(w, j);
-        bool good;
-        if (pow2) {
-          v[j] = pshift >= 32 ? 0u : (word >> pshift);
-          good = true;
-        } else {
-          good = range_map(word, s, thr, &v[j]);
-        }
-        if (good && tj >= t && tj < last_word) ok |= 1u << j;
-      }
-    }
-    const uint32_t cnt = __popc(ok);
-    uint32_t total;
-    uint32_t p = done + block_scan_excl(cnt, scr, &total);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (ok & (1u << j)) {
-        if (p < need) {
-          sink(p, v[j]);
-          if (p == need - 1) scr[8] = static_cast<uint32_t>(((blk << 2) + j + 1) - t0);
-        }
-        ++p;
-      }
-    }
-    done += total;
-    t = last_word;
-    __syncthreads();
-  }
-  next = t0 + scr[8];
-  __syncthreads();
-  return next;
-}
-
-// ---------------------------------------------------------------------------
-// Counting sort of keys[0..n) by their top bits, then exact ranking inside
-// each bucket; keys[] ends sorted ascending with equal values adjacent.
-// Returns the number of entries equal to an earlier one (duplicates).
-// shift: key >> shift is the bucket, nb buckets.
-// ---------------------------------------------------------------------------
-__device__ uint32_t bucket_sort(uint32_t* keys, uint32_t* tmp, uint32_t* buck, uint32_t* scr,
-                                uint32_t n, uint32_t shift, uint32_t nb) {
-  constexpr int R = kKeys / kLeafBlock;  // 16 keys per thread at most
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t b = tid; b < nb; b += kLeafBlock) buck[b] = 0;
-  if (tid == 0) scr[9] = 0;
-  __syncthreads();
-  uint32_t key[R];
-  uint32_t slot[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * kLeafBlock;
-    if (i < n) {
-      key[r] = keys[i];
-      slot[r] = atomicAdd(&buck[key[r] >> shift], 1u);
-    }
-  }
-  __syncthreads();
-  // exclusive scan of the bucket counts: thread tid owns a contiguous run
-  const uint32_t per = (nb + kLeafBlock - 1) / kLeafBlock;
-  const uint32_t b0 = tid * per;
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < per; ++k) {
-    const uint32_t b = b0 + k;
-    if (b < nb) run += buck[b];
-  }
-  uint32_t total;
-  uint32_t acc = block_scan_excl(run, scr, &total);
-  for (uint32_t k = 0; k < per; ++k) {
-    const uint32_t b = b0 + k;
-    if (b < nb) {
-      const uint32_t c = buck[b];
-      buck[b] = acc;
-      acc += c;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * kLeafBlock;
-    if (i < n) tmp[buck[key[r] >> shift] + slot[r]] = key[r];
-  }
-  __syncthreads();
-  uint32_t dups = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * kLeafBlock;
-    if (i < n) {
-      const uint32_t x = tmp[i];
-      const uint32_t b = x >> shift;
-      const uint32_t s = buck[b];
-      const uint32_t e = (b + 1 < nb) ? buck[b + 1] : n;
-      uint32_t lt = 0, eq = 0;
-      for (uint32_t j = s; j < e; ++j) {
-        const uint32_t y = tmp[j];
-        lt += (y < x) ? 1u : 0u;
-        eq += (y == x && j < i) ? 1u : 0u;
-      }
-      keys[s + lt + eq] = x;
-      dups += eq ? 1u : 0u;
-    }
-  }
-  if (dups) atomicAdd(&scr[9], dups);
-  __syncthreads();
-  const uint32_t d = scr[9];
-  __syncthreads();
-  return d;
-}
-
-// keys[0..n) sorted with equal values adjacent -> distinct values in
-// keys[0..d); returns d.
-__device__ uint32_t compact_distinct(uint32_t* keys, uint32_t* tmp, uint32_t* scr, uint32_t n) {
-  const uint32_t tid = threadIdx.x;
-  const uint32_t per = (n + kLeafBlock - 1) / kLeafBlock;
-  const uint32_t i0 = tid * per;
-  uint32_t c = 0;
-  for (uint32_t k = 0; k < per; ++k) {
-    const uint32_t i = i0 + k;
-    if (i < n && (i == 0 || keys[i] != keys[i - 1])) ++c;
-  }
-  uint32_t total;
-  uint32_t p = block_scan_excl(c, scr, &total);
-  for (uint32_t k = 0; k < per; ++k) {
-    const uint32_t i = i0 + k;
-    if (i < n && (i == 0 || keys[i] != keys[i - 1])) tmp[p++] = keys[i];
-  }
-  __syncthreads();
-  for (uint32_t i = tid; i < total; i += kLeafBlock) keys[i] = tmp[i];
-  __syncthreads();
-  return total;
-}
-
 __device__ __forceinline__ void store_out(uint64_t* out, uint64_t v) {
   __builtin_nontemporal_store(v, out);
 }
 
-// Write base + 1 + vals[i] for i < n, coalesced.
-__device__ __forceinline__ void write_sorted(uint64_t* out, uint64_t base, const uint32_t* vals,
-                                             uint32_t n) {
-  for (uint32_t i = threadIdx.x; i < n; i += kLeafBlock)
-    store_out(out + i, base + 1 + static_cast<uint64_t>(vals[i]));
-}
+// ---------------------------------------------------------------------------
+// LDS layout of a leaf work-group (32-bit words).
+//   [0, kRegionA)            sparse: keys | tmp      dense: positions
+//   [kRegionA, +kRegionB)    sparse: bucket counts   dense: kept | mask
+//   [.., +kCacheWords)       leaf-job records read ahead
+//   [.., +kScratch)          scan scratch
+// ---------------------------------------------------------------------------
+constexpr uint32_t kKeys = kMaxN0;                    // 4096 keys
+constexpr uint32_t kDenseCap = 2 * kMaxN0 + 64;        // largest accepted n'
+constexpr uint32_t kRegionA = 2 * kMaxN0 + 128;        // >= kDenseCap + 1
+constexpr uint32_t kBuckets = kMaxN0;                  // most buckets used
+constexpr uint32_t kBucketPad = 3;                     // one pad word per 8
+constexpr uint32_t kRegionB = kBuckets + (kBuckets >> kBucketPad);
+constexpr uint32_t kMaskWords = (kDenseCap + 32) / 32 + 1;
+static_assert(kKeys + kMaskWords <= kRegionB, "dense kept values + mask fit region B");
+constexpr uint32_t kCacheLeaves = 32;
+constexpr uint32_t kLeafWords = sizeof(Leaf) / 4;
+constexpr uint32_t kCacheWords = kCacheLeaves * kLeafWords;
+constexpr uint32_t kScratch = 64;
+constexpr uint32_t kSmemWords = kRegionA + kRegionB + kCacheWords + kScratch;
+// scratch words: [0, 16) scan; 16 next-word offset; 17 duplicate count
+constexpr uint32_t kScrNext = 16, kScrDups = 17;
+
+__device__ __forceinline__ uint32_t bpad(uint32_t b) { return b + (b >> kBucketPad); }
+
+struct LeafSmem {
+  uint32_t* keys;  // kKeys
+  uint32_t* tmp;   // kKeys
+  uint32_t* buck;  // kRegionB (padded bucket counters)
+  uint32_t* kept;  // = buck, dense
+  uint32_t* mask;  // after kept, dense
+  uint32_t* scr;   // kScratch
+};
 
 struct RangeInfo {
   uint64_t s;
   uint32_t thr;
   bool pow2;
-  uint32_t pshift;  // for pow2: value = word >> pshift
+  uint32_t pshift;  // pow2: value = word >> pshift (32: value 0)
 };
 
 __device__ __forceinline__ RangeInfo range_info(uint64_t s) {
@@ -295,62 +114,247 @@ __device__ __forceinline__ RangeInfo range_info(uint64_t s) {
   return r;
 }
 
-// Bucket parameters for keys < range and about n keys.
+// ---------------------------------------------------------------------------
+// The first `need` non-void values in [0, s) of a 32-bit stream, from word
+// t0 on, delivered in stream order to sink(p, value), p = 0..need-1.
+// Returns the word index just after the last value taken.  For a power-of-two
+// range no word is void and value p is word t0+p.  Otherwise each round
+// examines at most as many words as values are still wanted (a void costs a
+// further round) and a block scan orders the survivors.
+// ---------------------------------------------------------------------------
+template <int B, class Sink>
+__device__ uint64_t take_values(const Stream& st, uint64_t t0, uint32_t need, const RangeInfo& ri,
+                                uint32_t* scr, Sink sink) {
+  if (need == 0) return t0;
+  if (ri.pow2) {
+    const uint64_t t1 = t0 + need;
+    for (uint64_t blk = (t0 >> 2) + threadIdx.x; (blk << 2) < t1; blk += B) {
+      const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t t = (blk << 2) + j;
+        if (t >= t0 && t < t1) {
+          const uint32_t word = pick(w, j);
+          sink(static_cast<uint32_t>(t - t0), ri.pshift >= 32 ? 0u : (word >> ri.pshift));
+        }
+      }
+    }
+    __syncthreads();
+    return t1;
+  }
+  uint32_t done = 0;
+  uint64_t t = t0;
+  while (done < need) {
+    const uint32_t want = need - done;
+    const uint64_t first_blk = t >> 2;
+    uint64_t last_word = t + want;
+    const uint64_t reach = (first_blk + B) << 2;
+    if (last_word > reach) last_word = reach;
+    const uint64_t blk = first_blk + threadIdx.x;
+    uint32_t v[4];
+    uint32_t ok = 0;
+    if ((blk << 2) < last_word) {
+      const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t tj = (blk << 2) + j;
+        const bool good = range_map(pick(w, j), ri.s, ri.thr, &v[j]);
+        if (good && tj >= t && tj < last_word) ok |= 1u << j;
+      }
+    }
+    uint32_t total;
+    uint32_t p = done + block_scan_excl<B, uint32_t>(__popc(ok), scr, &total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (ok & (1u << j)) {
+        if (p < need) {
+          sink(p, v[j]);
+          if (p == need - 1) scr[kScrNext] = static_cast<uint32_t>(((blk << 2) + j + 1) - t0);
+        }
+        ++p;
+      }
+    }
+    done += total;
+    t = last_word;
+    __syncthreads();
+  }
+  const uint64_t next = t0 + scr[kScrNext];
+  __syncthreads();
+  return next;
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort of keys[0..n) by their top bits (bucket = key >> shift, nb
+// buckets), then exact ranking inside each bucket: keys[] ends ascending
+// with equal values adjacent.  Returns how many entries equal an earlier one.
+// Bucket counters live at padded indices so that the per-thread runs of the
+// counter scan fall in distinct LDS banks.
+// ---------------------------------------------------------------------------
+template <int B>
+__device__ uint32_t bucket_sort(uint32_t* keys, uint32_t* tmp, uint32_t* buck, uint32_t* scr,
+                                uint32_t n, uint32_t shift, uint32_t nb) {
+  constexpr int R = kKeys / B;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < bpad(nb); b += B) buck[b] = 0;
+  if (tid == 0) scr[kScrDups] = 0;
+  __syncthreads();
+  uint32_t key[R], slot[R], bk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = tid + r * B;
+    if (i < n) {
+      key[r] = keys[i];
+      bk[r] = bpad(key[r] >> shift);
+      slot[r] = atomicAdd(&buck[bk[r]], 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t per = (nb + B - 1) / B;
+  const uint32_t b0 = tid * per;
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < nb) run += buck[bpad(b0 + k)];
+  uint32_t total;
+  uint32_t acc = block_scan_excl<B, uint32_t>(run, scr, &total);
+  for (uint32_t k = 0; k < per; ++k) {
+    if (b0 + k < nb) {
+      const uint32_t c = buck[bpad(b0 + k)];
+      buck[bpad(b0 + k)] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = tid + r * B;
+    if (i < n) {
+      slot[r] += buck[bk[r]];  // position in bucket order
+      tmp[slot[r]] = key[r];
+    }
+  }
+  __syncthreads();
+  uint32_t dups = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = tid + r * B;
+    if (i < n) {
+      const uint32_t x = key[r];
+      const uint32_t b = x >> shift;
+      const uint32_t s = buck[bpad(b)];
+      const uint32_t e = (b + 1 < nb) ? buck[bpad(b + 1)] : n;
+      uint32_t lt = 0, eq = 0;
+      for (uint32_t j = s; j < e; ++j) {
+        const uint32_t y = tmp[j];
+        lt += (y < x) ? 1u : 0u;
+        eq += (y == x && j < slot[r]) ? 1u : 0u;
+      }
+      keys[s + lt + eq] = x;
+      dups += eq ? 1u : 0u;
+    }
+  }
+  if (dups) atomicAdd(&scr[kScrDups], dups);
+  __syncthreads();
+  const uint32_t d = scr[kScrDups];
+  __syncthreads();
+  return d;
+}
+
+// keys[0..n) ascending with equal values adjacent -> the distinct values in
+// keys[0..d); returns d.
+template <int B>
+__device__ uint32_t compact_distinct(uint32_t* keys, uint32_t* tmp, uint32_t* scr, uint32_t n) {
+  constexpr int R = kKeys / B;
+  const uint32_t tid = threadIdx.x;
+  // contiguous runs per thread keep the scan order equal to index order
+  const uint32_t per = (n + B - 1) / B;
+  const uint32_t i0 = tid * per;
+  uint32_t c = 0;
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t i = i0 + k;
+    if (i < n && (i == 0 || keys[i] != keys[i - 1])) ++c;
+  }
+  uint32_t total;
+  uint32_t p = block_scan_excl<B, uint32_t>(c, scr, &total);
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t i = i0 + k;
+    if (i < n && (i == 0 || keys[i] != keys[i - 1])) tmp[p++] = keys[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = tid + r * B;
+    if (i < total) keys[i] = tmp[i];
+  }
+  __syncthreads();
+  return total;
+}
+
+// out[i] = base + 1 + vals[i] for i < n, coalesced.
+template <int B>
+__device__ __forceinline__ void write_sorted(uint64_t* out, uint64_t base, const uint32_t* vals,
+                                             uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += B)
+    store_out(out + i, base + 1 + static_cast<uint64_t>(vals[i]));
+}
+
+// Buckets for keys < range, about n keys: 2^lb buckets, lb = bits of n,
+// clamped to [6, 12].
 __device__ __forceinline__ void bucket_params(uint64_t range, uint32_t n, uint32_t* shift,
                                               uint32_t* nb) {
   const uint32_t kb = bit_length(range - 1);
   uint32_t lb = bit_length(n > 1 ? n - 1 : 1);
-  if (lb < 6) lb = 6;
-  if (lb > 12) lb = 12;
+  lb = lb < 6 ? 6 : (lb > 12 ? 12 : lb);
   *shift = kb > lb ? kb - lb : 0u;
-  const uint64_t used = ((range - 1) >> *shift) + 1;
-  *nb = static_cast<uint32_t>(used);
+  *nb = static_cast<uint32_t>(((range - 1) >> *shift) + 1);
 }
 
 // ---------------------------------------------------------------------------
-// Sparse leaf: Algorithm H semantics.
+// Sparse leaf: Algorithm H semantics, computed in rounds.
 // ---------------------------------------------------------------------------
-__device__ void leaf_sparse(const Leaf& L, const Instance& I, uint64_t* out, LeafSmem& sm) {
-  const uint32_t nv = static_cast<uint32_t>(L.nv);
+template <int B>
+__device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
+  const uint32_t nv = L.nv;
   const RangeInfo ri = range_info(L.Nv);
   uint32_t shift, nb;
   bucket_params(L.Nv, nv, &shift, &nb);
-  const Stream st = make_stream(I.seed, L.id, kLeaf, 0);
+  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
+  uint32_t* keys = sm.keys;
   uint32_t have = 0;
   uint64_t t = 0;
-  uint32_t* keys = sm.keys;
   for (;;) {
     const uint32_t base = have;
-    t = take_values(st, t, nv - have, ri.s, ri.thr, ri.pow2, ri.pshift, sm.scr,
-                    [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
-    const uint32_t dups = bucket_sort(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
+    t = take_values<B>(st, t, nv - have, ri, sm.scr,
+                       [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
+    const uint32_t dups = bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
     if (dups == 0) break;
-    have = compact_distinct(keys, sm.tmp, sm.scr, nv);
+    have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
   }
-  write_sorted(out + I.out_offset + L.off, L.lo, keys, nv);
+  write_sorted<B>(out + L.off, L.lo, keys, nv);
 }
 
 // With-replacement leaf: the first n_v non-void draws, sorted, repeats kept.
-__device__ void leaf_wr(const Leaf& L, const Instance& I, uint64_t* out, LeafSmem& sm) {
-  const uint32_t nv = static_cast<uint32_t>(L.nv);
+template <int B>
+__device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
+  const uint32_t nv = L.nv;
   const RangeInfo ri = range_info(L.Nv);
   uint32_t shift, nb;
   bucket_params(L.Nv, nv, &shift, &nb);
-  const Stream st = make_stream(I.seed, L.id, kWrLeaf, 0);
+  const Stream st = make_stream(L.seed, L.id, kWrLeaf, 0);
   uint32_t* keys = sm.keys;
-  take_values(st, 0, nv, ri.s, ri.thr, ri.pow2, ri.pshift, sm.scr,
-              [&](uint32_t p, uint32_t v) { keys[p] = v; });
-  bucket_sort(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
-  write_sorted(out + I.out_offset + L.off, L.lo, keys, nv);
+  take_values<B>(st, 0, nv, ri, sm.scr, [&](uint32_t p, uint32_t v) { keys[p] = v; });
+  bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
+  write_sorted<B>(out + L.off, L.lo, keys, nv);
 }
 
 // ---------------------------------------------------------------------------
 // Dense leaf: Algorithm B with geometric skips and repair.
 // ---------------------------------------------------------------------------
-__device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, LeafSmem& sm) {
+template <int B>
+__device__ void leaf_dense(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const uint32_t tid = threadIdx.x;
-  const uint32_t nv = static_cast<uint32_t>(L.nv);
-  const uint32_t Nv = static_cast<uint32_t>(L.Nv);  // < 16 * 4096 here
+  const uint32_t nv = L.nv;
+  const uint32_t Nv = static_cast<uint32_t>(L.Nv);  // < 64 * 4096 here
+  const uint32_t n0 = L.flags >> 8;
   const uint32_t rho_num = nv + 3u * static_cast<uint32_t>(isqrt64(nv)) + 8u;
   const bool full = rho_num >= Nv;
   float cg = 0.0f;
@@ -358,18 +362,17 @@ __device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, Leaf
     const float rho = static_cast<float>(rho_num) / static_cast<float>(Nv);
     cg = static_cast<float>(1.0 / log64(1.0 - static_cast<double>(rho)));
   }
-  const uint32_t cap = 2u * I.n0 + 64u;
+  const uint32_t cap = 2u * n0 + 64u;
   uint32_t* pos = sm.keys;  // region A: up to kDenseCap + 1 positions
-  uint32_t* kept = sm.buck; // region B: n_v kept values
   for (uint32_t attempt = 0;; ++attempt) {
     uint32_t hits;  // n'
     if (full) {
       hits = Nv;
     } else {
-      const Stream st = make_stream(I.seed, L.id, kBern, attempt);
+      const Stream st = make_stream(L.seed, L.id, kBern, attempt);
       int64_t last = -1;  // position of the last word of the previous round
       uint32_t count = 0;
-      for (uint32_t blk0 = 0;; blk0 += kLeafBlock) {
+      for (uint32_t blk0 = 0;; blk0 += B) {
         const uint4 w = philox_block(st, blk0 + tid);
         int32_t inc[4];
         uint32_t sum = 0;
@@ -379,7 +382,7 @@ __device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, Leaf
           sum += static_cast<uint32_t>(inc[j]);
         }
         uint32_t total;
-        const uint32_t before = block_scan_excl(sum, sm.scr, &total);
+        const uint32_t before = block_scan_excl<B, uint32_t>(sum, sm.scr, &total);
         int64_t p = last + static_cast<int64_t>(before);
         uint32_t in = 0;
 #pragma unroll
@@ -387,16 +390,24 @@ __device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, Leaf
           p += inc[j];
           if (p < static_cast<int64_t>(Nv)) {
             ++in;
-            const uint32_t idx = count + 4u * tid + j;  // stream index t = hit index
+            const uint32_t idx = count + 4u * tid + j;  // stream index = hit index
             if (idx <= cap) pos[idx] = static_cast<uint32_t>(p);
           }
         }
-        // hits of this round: positions below Nv form a prefix of the round
-        uint32_t tot_in;
-        block_scan_excl(in, sm.scr, &tot_in);
-        count += tot_in;
+        // positions below Nv form a prefix of the round: count the threads
+        // with all four in, plus the one partial thread
+        const uint32_t full_threads = static_cast<uint32_t>(__syncthreads_count(in == 4 ? 1 : 0));
+        const uint32_t partial = static_cast<uint32_t>(__syncthreads_count(in > 0 && in < 4 ? 1 : 0));
+        uint32_t round_in = 4u * full_threads;
+        if (partial) {
+          if (in > 0 && in < 4) sm.scr[kScrNext] = in;
+          __syncthreads();
+          round_in += sm.scr[kScrNext];
+          __syncthreads();
+        }
+        count += round_in;
         last += static_cast<int64_t>(total);
-        if (tot_in < 4u * kLeafBlock || count > cap) break;
+        if (round_in < 4u * B || count > cap) break;
       }
       hits = count;
       if (hits < nv || hits > cap) continue;
@@ -405,27 +416,27 @@ __device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, Leaf
     // stream mapped into [0, hits).
     const uint32_t r = hits - nv;
     const uint32_t mwords = (hits + 31) / 32;
-    for (uint32_t i = tid; i < mwords; i += kLeafBlock) sm.mask[i] = 0;
+    for (uint32_t i = tid; i < mwords; i += B) sm.mask[i] = 0;
     __syncthreads();
     if (r > 0) {
-      const Stream sr = make_stream(I.seed, L.id, kRepair, attempt);
+      const Stream sr = make_stream(L.seed, L.id, kRepair, attempt);
       const RangeInfo ri = range_info(hits);
       uint32_t have = 0;
       uint64_t t = 0;
       for (;;) {
-        t = take_values(sr, t, r - have, ri.s, ri.thr, ri.pow2, ri.pshift, sm.scr,
-                        [&](uint32_t, uint32_t v) { atomicOr(&sm.mask[v >> 5], 1u << (v & 31)); });
-        __syncthreads();
+        t = take_values<B>(sr, t, r - have, ri, sm.scr, [&](uint32_t, uint32_t v) {
+          atomicOr(&sm.mask[v >> 5], 1u << (v & 31));
+        });
         uint32_t c = 0;
-        for (uint32_t i = tid; i < mwords; i += kLeafBlock) c += __popc(sm.mask[i]);
+        for (uint32_t i = tid; i < mwords; i += B) c += __popc(sm.mask[i]);
         uint32_t total;
-        block_scan_excl(c, sm.scr, &total);
+        block_scan_excl<B, uint32_t>(c, sm.scr, &total);
         have = total;
         if (have == r) break;
       }
     }
     // Compact the kept hits (ascending position) into kept[0..nv).
-    const uint32_t per = (hits + kLeafBlock - 1) / kLeafBlock;
+    const uint32_t per = (hits + B - 1) / B;
     const uint32_t i0 = tid * per;
     uint32_t c = 0;
     for (uint32_t k = 0; k < per; ++k) {
@@ -433,54 +444,73 @@ __device__ void leaf_dense(const Leaf& L, const Instance& I, uint64_t* out, Leaf
       if (i < hits && !((sm.mask[i >> 5] >> (i & 31)) & 1u)) ++c;
     }
     uint32_t total;
-    uint32_t o = block_scan_excl(c, sm.scr, &total);
+    uint32_t o = block_scan_excl<B, uint32_t>(c, sm.scr, &total);
     for (uint32_t k = 0; k < per; ++k) {
       const uint32_t i = i0 + k;
-      if (i < hits && !((sm.mask[i >> 5] >> (i & 31)) & 1u)) kept[o++] = full ? i : pos[i];
+      if (i < hits && !((sm.mask[i >> 5] >> (i & 31)) & 1u)) sm.kept[o++] = full ? i : pos[i];
     }
     __syncthreads();
-    write_sorted(out + I.out_offset + L.off, L.lo, kept, nv);
+    write_sorted<B>(out + L.off, L.lo, sm.kept, nv);
     break;
   }
 }
 
 // Constant leaf of a with-replacement tree: N_v = 1, every draw is lo+1.
-__device__ void leaf_fill(const Leaf& L, const Instance& I, uint64_t* out) {
-  uint64_t* o = out + I.out_offset + L.off;
-  for (uint64_t i = threadIdx.x; i < L.nv; i += kLeafBlock) store_out(o + i, L.lo + 1);
+template <int B>
+__device__ void leaf_fill(const Leaf& L, uint64_t* out) {
+  uint64_t* o = out + L.off;
+  for (uint32_t i = threadIdx.x; i < L.nv; i += B) store_out(o + i, L.lo + 1);
 }
 
-__global__ __launch_bounds__(kLeafBlock) void k_leaf(const Instance* __restrict__ inst,
-                                                     const Leaf* __restrict__ leaves,
-                                                     uint64_t leaf_cap, uint64_t* out,
-                                                     Control* ctl) {
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
+                                            uint64_t* out, const Control* ctl) {
   __shared__ uint32_t smem[kSmemWords];
-  __shared__ unsigned long long cur;
   LeafSmem sm;
   sm.keys = smem;
   sm.tmp = smem + kKeys;
   sm.buck = smem + kRegionA;
-  sm.mask = smem + kRegionA + kRegionB;
-  sm.scr = smem + kRegionA + kRegionB + kMaskWords;
-  const unsigned long long n_leaves =
-      ctl->leaf_count < leaf_cap ? ctl->leaf_count : static_cast<unsigned long long>(leaf_cap);
-  for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(&ctl->leaf_ticket, 1ull);
-    __syncthreads();
-    const unsigned long long i = cur;
-    __syncthreads();
+  sm.kept = sm.buck;
+  sm.mask = sm.buck + kKeys;
+  uint32_t* cache = smem + kRegionA + kRegionB;
+  sm.scr = cache + kCacheWords;
+  const unsigned long long cnt = ctl->leaf_count;
+  const uint64_t n_leaves = cnt < leaf_cap ? cnt : leaf_cap;
+  const uint64_t G = gridDim.x;
+  for (uint64_t j = 0;; ++j) {
+    const uint64_t i = blockIdx.x + j * G;
     if (i >= n_leaves) break;
-    const Leaf L = leaves[i];
-    const Instance I = inst[L.inst];
-    if (I.variant == 1) {
-      if (L.Nv == 1)
-        leaf_fill(L, I, out);
-      else
-        leaf_wr(L, I, out, sm);
-    } else if (static_cast<uint64_t>(I.dense_ratio) * L.nv >= L.Nv) {
-      leaf_dense(L, I, out, sm);
-    } else {
-      leaf_sparse(L, I, out, sm);
+    const uint32_t slot = static_cast<uint32_t>(j % kCacheLeaves);
+    if (slot == 0) {
+      // read the next kCacheLeaves job records of this work-group into LDS
+      const uint32_t tid = threadIdx.x;
+      if (tid < kCacheLeaves * 3) {
+        const uint32_t which = tid / 3, part = tid % 3;
+        const uint64_t li = i + static_cast<uint64_t>(which) * G;
+        if (li < n_leaves) {
+          const uint4 v = reinterpret_cast<const uint4*>(leaves + li)[part];
+          reinterpret_cast<uint4*>(cache + which * kLeafWords)[part] = v;
+        }
+      }
+      __syncthreads();
+    }
+    Leaf L;
+    {
+      const uint4* c = reinterpret_cast<const uint4*>(cache + slot * kLeafWords);
+      const uint4 a = c[0], b = c[1], d = c[2];
+      L.id = static_cast<uint64_t>(a.x) | (static_cast<uint64_t>(a.y) << 32);
+      L.lo = static_cast<uint64_t>(a.z) | (static_cast<uint64_t>(a.w) << 32);
+      L.Nv = static_cast<uint64_t>(b.x) | (static_cast<uint64_t>(b.y) << 32);
+      L.off = static_cast<uint64_t>(b.z) | (static_cast<uint64_t>(b.w) << 32);
+      L.seed = static_cast<uint64_t>(d.x) | (static_cast<uint64_t>(d.y) << 32);
+      L.nv = d.z;
+      L.flags = d.w;
+    }
+    switch (L.flags & 3u) {
+      case kKindSparse: leaf_sparse<B>(L, out, sm); break;
+      case kKindDense: leaf_dense<B>(L, out, sm); break;
+      case kKindWr: leaf_wr<B>(L, out, sm); break;
+      default: leaf_fill<B>(L, out); break;
     }
     __syncthreads();
   }
@@ -500,11 +530,17 @@ __device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I)
                         : hypergeometric(v.nv, l, v.Nv, I.seed, v.id);
 }
 
-__device__ __forceinline__ void emit(const Node& v, uint32_t inst_idx, Leaf* leaves,
-                                     uint64_t cap, Control* ctl) {
+__device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* leaves, uint64_t cap,
+                                     Control* ctl) {
+  uint32_t kind;
+  if (I.variant == 1)
+    kind = v.Nv == 1 ? kKindFill : kKindWr;
+  else
+    kind = static_cast<uint64_t>(I.dense_ratio) * v.nv >= v.Nv ? kKindDense : kKindSparse;
   uint64_t pieces = 1;
-  if (v.Nv == 1 && v.nv > kFillPiece) pieces = (v.nv + kFillPiece - 1) / kFillPiece;
-  const unsigned long long base = atomicAdd(&ctl->leaf_count, static_cast<unsigned long long>(pieces));
+  if (kind == kKindFill && v.nv > kFillPiece) pieces = (v.nv + kFillPiece - 1) / kFillPiece;
+  const unsigned long long base =
+      atomicAdd(&ctl->leaf_count, static_cast<unsigned long long>(pieces));
   for (uint64_t j = 0; j < pieces; ++j) {
     if (base + j >= cap) {
       atomicOr(&ctl->error, kErrLeafCapacity);
@@ -514,10 +550,11 @@ __device__ __forceinline__ void emit(const Node& v, uint32_t inst_idx, Leaf* lea
     L.id = v.id;
     L.lo = v.lo;
     L.Nv = v.Nv;
-    L.off = v.off + j * kFillPiece;
-    L.nv = (pieces == 1) ? v.nv : ((j + 1 < pieces) ? kFillPiece : v.nv - j * kFillPiece);
-    L.inst = inst_idx;
-    L.pad = 0;
+    L.off = I.out_offset + v.off + j * kFillPiece;
+    L.seed = I.seed;
+    L.nv = static_cast<uint32_t>(pieces == 1 ? v.nv
+                                             : ((j + 1 < pieces) ? kFillPiece : v.nv - j * kFillPiece));
+    L.flags = kind | (I.n0 << 8);
     leaves[base + j] = L;
   }
 }
@@ -541,7 +578,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     if (v.nv == 0) return;
     if (is_leaf(v, I)) {
       const uint32_t below = I.cut - d;
-      if ((g & ((1ull << below) - 1)) == 0) emit(v, lo, leaves, leaf_cap, ctl);
+      if ((g & ((1ull << below) - 1)) == 0) emit(v, I, leaves, leaf_cap, ctl);
       return;
     }
     const uint64_t L = split_left(v, I);
@@ -559,7 +596,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     for (;;) {
       if (v.nv == 0) break;
       if (is_leaf(v, I)) {
-        emit(v, lo, leaves, leaf_cap, ctl);
+        emit(v, I, leaves, leaf_cap, ctl);
         break;
       }
       const uint64_t L = split_left(v, I);
@@ -608,6 +645,7 @@ constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagIncl = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 26;
+constexpr uint32_t kBernLds = kRegionA + kKeys;
 
 // One pass over the chunk's geometric stream.  Hits i < lds_cap go to pos[]
 // when write == false; when write == true, hits i >= lds_cap are written
@@ -616,11 +654,12 @@ __device__ uint64_t bern_pass(const Stream& st, uint64_t len, int fp32, double c
                               uint32_t* pos, uint32_t lds_cap, bool write, uint64_t* out,
                               uint64_t out_first, uint64_t capacity, uint64_t base,
                               uint64_t* scr64, uint32_t* scr) {
+  constexpr int B = kBernBlock;
   const uint32_t tid = threadIdx.x;
   int64_t last = -1;
   uint64_t count = 0;
   const uint32_t per = fp32 ? 4u : 2u;
-  for (uint32_t blk0 = 0;; blk0 += kLeafBlock) {
+  for (uint32_t blk0 = 0;; blk0 += B) {
     const uint4 w = philox_block(st, blk0 + tid);
     uint64_t inc[4];
     uint64_t sum = 0;
@@ -643,7 +682,7 @@ __device__ uint64_t bern_pass(const Stream& st, uint64_t len, int fp32, double c
       inc[2] = inc[3] = 0;
     }
     uint64_t total;
-    const uint64_t before = block_scan_excl64(sum, scr64, &total);
+    const uint64_t before = block_scan_excl<B, uint64_t>(sum, scr64, &total);
     int64_t p = last + static_cast<int64_t>(before);
     uint32_t in = 0;
     for (uint32_t j = 0; j < per; ++j) {
@@ -659,21 +698,21 @@ __device__ uint64_t bern_pass(const Stream& st, uint64_t len, int fp32, double c
       }
     }
     uint32_t tot_in;
-    block_scan_excl(in, scr, &tot_in);
+    block_scan_excl<B, uint32_t>(in, scr, &tot_in);
     count += tot_in;
     last += static_cast<int64_t>(total);
-    if (tot_in < per * kLeafBlock) break;
+    if (tot_in < per * B) break;
   }
   return count;
 }
 
-__global__ __launch_bounds__(kLeafBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
+__global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
                                                      uint64_t n_chunks, int fp32, double c64,
                                                      float c32, unsigned long long* status,
                                                      uint64_t* out, uint64_t capacity,
                                                      uint64_t* count_dev, Control* ctl,
                                                      uint32_t lds_cap) {
-  __shared__ uint32_t pos[kRegionA + kRegionB];
+  __shared__ uint32_t pos[kBernLds];
   __shared__ uint32_t scr[32];
   __shared__ uint64_t scr64[8];
   __shared__ unsigned long long cur, excl;
@@ -724,7 +763,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_bern(uint64_t N, uint64_t seed, 
     __syncthreads();
     const uint64_t first = excl;
     const uint64_t held = cnt < lds_cap ? cnt : lds_cap;
-    for (uint64_t i = threadIdx.x; i < held; i += kLeafBlock)
+    for (uint64_t i = threadIdx.x; i < held; i += kBernBlock)
       if (first + i < capacity) store_out(out + first + i, base + static_cast<uint64_t>(pos[i]) + 1);
     if (cnt > lds_cap)
       bern_pass(st, len, fp32, c64, c32, pos, lds_cap, true, out, first, capacity, base, scr64, scr);
@@ -807,8 +846,9 @@ hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hip
 
 int leaf_occupancy() {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_leaf),
-                                                   kLeafBlock, 0) != hipSuccess || occ <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_leaf<kLeafBlock>), kLeafBlock, 0) != hipSuccess ||
+      occ <= 0)
     occ = 2;
   return occ;
 }
@@ -823,10 +863,10 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(const Instance* inst, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
-                       Control* ctl, uint32_t grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(kLeafBlock), 0, stream, inst, leaves, leaf_cap, out,
-                     ctl);
+hipError_t launch_leaf(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                       uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_leaf<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves, leaf_cap,
+                     out, ctl);
   return hipGetLastError();
 }
 
@@ -835,7 +875,7 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t* out, uint64_t capacity, uint64_t* count_dev, Control* ctl,
                             uint32_t grid, uint32_t lds_cap, hipStream_t stream) {
   (void)p;
-  hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kLeafBlock), 0, stream, N, seed, chunk, n_chunks,
+  hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk, n_chunks,
                      fp32, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
   return hipGetLastError();
 }

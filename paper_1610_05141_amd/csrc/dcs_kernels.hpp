@@ -27,12 +27,22 @@ struct Node {
   uint64_t id, lo, Nv, nv, off;
 };
 
-// A leaf job for the leaf kernel: a node plus the instance it belongs to.
+// A leaf job for the leaf kernel, self-contained: the node, its instance's
+// seed, the absolute output offset of its first value, and its kind.
 struct Leaf {
-  uint64_t id, lo, Nv, nv, off;
-  uint32_t inst;
-  uint32_t pad;
+  uint64_t id, lo, Nv;
+  uint64_t off;   // absolute: instance output offset + node offset
+  uint64_t seed;
+  uint32_t nv;    // < n0 <= 4096, or <= kFillPiece for constant pieces
+  uint32_t flags; // kind (bits 0-1) | n0 << 8
 };
+static_assert(sizeof(Leaf) == 48, "leaf record layout");
+
+// Leaf kinds.
+constexpr uint32_t kKindSparse = 0;  // Algorithm H semantics
+constexpr uint32_t kKindDense = 1;   // Algorithm B with repair
+constexpr uint32_t kKindWr = 2;      // with replacement: sorted draws
+constexpr uint32_t kKindFill = 3;    // with replacement, N_v = 1: constant
 
 // Control block at the start of a workspace.
 struct Control {
@@ -49,7 +59,8 @@ constexpr unsigned kErrStackDepth = 2u;     // tree deeper than the planned stac
 constexpr unsigned kErrSpinLimit = 4u;      // Bernoulli look-back waited too long
 constexpr unsigned kErrLeafTooLarge = 8u;   // a leaf exceeds the kernel's LDS bound
 
-constexpr int kLeafBlock = 256;             // threads of a leaf work-group
+constexpr int kLeafBlock = 512;             // threads of a leaf work-group
+constexpr int kBernBlock = 256;             // threads of a Bernoulli work-group
 constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
 constexpr uint64_t kFillPiece = 1ull << 16; // constant-fill leaves are cut to this
 
@@ -65,8 +76,8 @@ int leaf_occupancy();
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
                        Leaf* leaves, uint64_t leaf_cap, Node* stacks, uint32_t stack_depth,
                        Control* ctl, hipStream_t stream);
-hipError_t launch_leaf(const Instance* inst, const Leaf* leaves, uint64_t leaf_cap,
-                       uint64_t* out, Control* ctl, uint32_t grid, hipStream_t stream);
+hipError_t launch_leaf(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                       uint32_t grid, hipStream_t stream);
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,

@@ -1,0 +1,55 @@
+"""The sample never depends on launch geometry (GPU): different numbers of
+leaf work-groups and different Algorithm P cut depths give identical bytes,
+equal to the oracle's.  Also a race detector: any order dependence inside a
+work-group or between work-groups would show up as a difference."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CASES = [  # (variant, n, N, seed, n0)
+    ("wor", 1 << 20, 1 << 32, 1, 4096),
+    ("wor", 300000, 700000, 3, 1024),
+    ("wor", 40000, 2**41 + 5, 4, 256),
+    ("wr", 200000, 3 * 10**6 + 1, 5, 512),
+]
+
+SCRIPT = r"""
+import hashlib, sys
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+import paper_1610_05141_amd as dcs
+for variant, n, N, seed, n0 in {cases!r}:
+    f = dcs.sample if variant == "wor" else dcs.sample_replacement
+    out = f(n, N, seed, n0=n0)
+    dcs.synchronize()
+    print(hashlib.sha256(out.cpu().numpy().tobytes()).hexdigest(), flush=True)
+"""
+
+
+def _run(env_extra):
+    env = dict(os.environ)
+    env.update(env_extra)
+    print(f"[gpu-step] geometry {env_extra}", flush=True)
+    r = subprocess.run([sys.executable, "-c", SCRIPT.format(root=ROOT, cases=CASES)],
+                       env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return r.stdout.split()
+
+
+def test_launch_geometry_invariance(ref):
+    want = []
+    for variant, n, N, seed, n0 in CASES:
+        v = ref.sample(n, N, seed, n0=n0) if variant == "wor" else ref.replacement(n, N, seed, n0=n0)
+        want.append(hashlib.sha256(v.astype(np.int64).tobytes()).hexdigest())
+    for env in [{}, {"DCS_LEAF_GRID": "1"}, {"DCS_LEAF_GRID": "7"},
+                {"DCS_LEAF_GRID": "5000"}, {"DCS_CUT_BIAS": "-4"},
+                {"DCS_CUT_BIAS": "3"}, {"DCS_LEAF_GRID": "13", "DCS_CUT_BIAS": "-20"}]:
+        assert _run(env) == want, env
