@@ -1,5 +1,6 @@
 """Benchmark: n = 2^30 distinct values of 1..2^48 (seed 7), sorted uint64,
-one MI355X.
+one MI355X; also the batched path against per-instance plain launches on
+4096 uneven instances, and serving latency (p50/p99) under Poisson arrivals.
 
 One step = one full sample (tree kernel + leaf kernel) into a resident 8 GiB
 output buffer.  Prints one JSON line: samples/s, the leaf kernel's achieved
@@ -54,6 +55,91 @@ def cpu_baseline(gpu_out, budget_s: float = 12.0):
     }
 
 
+def bench_batched(dcs, reps: int = 3):
+    """4096 uneven instances (n log-uniform in [2^8, 2^22], density in
+    [1e-6, 0.5], seeds 0..4095): one hipGraph-replayed batch vs one plain
+    dcs_sample call per instance on one stream (synchronized once)."""
+    import torch
+    from paper_1610_05141_amd.workloads import batched_instances
+    insts = batched_instances(4096)
+    specs, off = [], 0
+    for x in insts:
+        specs.append(dcs.InstanceSpec(n=x.n, N=x.N, seed=x.seed, out_offset=off))
+        off += x.n
+    total = off
+    out = torch.empty(total, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    b = dcs.Batch(specs)
+    with torch.cuda.stream(stream):
+        b.run(out, use_graph=True, stream=stream)  # capture + first replay
+    dcs.synchronize(stream)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            b.run(out, use_graph=True, stream=stream)
+    dcs.synchronize(stream)
+    batched_s = (time.perf_counter() - t0) / reps
+    # plain: one call per instance into the same buffer
+    with torch.cuda.stream(stream):
+        for s_, x in zip(specs, insts):
+            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream)
+    dcs.synchronize(stream)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for s_, x in zip(specs, insts):
+            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream)
+    dcs.synchronize(stream)
+    plain_s = time.perf_counter() - t0
+    b.close()
+    del out
+    torch.cuda.empty_cache()
+    return {
+        "workload": "4096 instances, n log-uniform in [2^8, 2^22], n/N log-uniform in "
+                    "[1e-6, 0.5], seeds 0..4095, without replacement",
+        "samples": total,
+        "batched_ms": batched_s * 1e3,
+        "batched_samples_per_s": total / batched_s,
+        "plain_ms": plain_s * 1e3,
+        "speedup_vs_plain": plain_s / batched_s,
+    }
+
+
+def bench_serving(dcs, rate: float = 20000.0, warm: int = 10000, timed: int = 100000):
+    """Open-loop Poisson arrivals at `rate`/s of instances drawn like the
+    batched workload (n capped at 2^24), admitted by output footprint under a
+    64 GiB arena; latency from scheduled arrival to completion."""
+    from paper_1610_05141_amd.workloads import batched_instances, poisson_arrivals
+    insts = batched_instances(warm + timed, n_cap_log2=24, key=0xC5)
+    srv = dcs.Server(arena_bytes=64 << 30, max_batch=4096, n_streams=4, auto_release=True)
+    reqs = [(x.n, x.N, x.seed) for x in insts]
+    t0 = dcs.Server.now() + 0.05
+    arr = [t0 + t for t in poisson_arrivals(len(reqs), rate, key=0xC5)]
+    srv.submit_schedule(reqs[:warm], arr[:warm])
+    srv.drain()
+    warm_stats = srv.stats()
+    srv.close()
+    # fresh server for the timed part so that the statistics hold only it
+    srv = dcs.Server(arena_bytes=64 << 30, max_batch=4096, n_streams=4, auto_release=True)
+    t1 = dcs.Server.now() + 0.05
+    base = arr[warm]
+    srv.submit_schedule(reqs[warm:], [t1 + (t - base) for t in arr[warm:]])
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": f"Poisson {rate:.0f} req/s, n log-uniform in [2^8, 2^22], density "
+                    "[1e-6, 0.5], 64 GiB admission cap, without replacement",
+        "requests": st["completed"],
+        "warmup_requests": warm_stats["completed"],
+        "p50_ms": st["p50_s"] * 1e3,
+        "p99_ms": st["p99_s"] * 1e3,
+        "max_ms": st["max_s"] * 1e3,
+        "samples_per_s": st["samples"] / st["span_s"] if st["span_s"] > 0 else None,
+        "offered_samples_per_s": rate * (sum(r[0] for r in reqs[warm:]) / max(timed, 1)),
+        "batches": st["batches"],
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +148,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -142,8 +230,19 @@ def main() -> int:
         "whole_step_write_GBs": BYTES_PER_SAMPLE * N_SAMPLE / (ms_per_step * 1e-3) / 1e9,
         "invariants_ok": props_ok,
     }
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched vs plain", file=sys.stderr, flush=True)
+        rec["batched"] = bench_batched(dcs)
+    if not args.no_serving:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        rec["serving"] = bench_serving(dcs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out = torch.empty(N_SAMPLE, dtype=torch.int64, device="cuda")
+        dcs.sample(N_SAMPLE, UNIVERSE, SEED, out=out, stream=stream, n0=N0)
+        dcs.synchronize(stream)
         rec["cpu_baseline"] = cpu_baseline(out)
     print(json.dumps(rec), flush=True)
     return 0

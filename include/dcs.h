@@ -149,6 +149,67 @@ int32_t dcs_batch_destroy(dcs_batch* batch);
 /* Total output elements of the batch (sum of n). */
 uint64_t dcs_batch_total(const dcs_batch* batch);
 
+/*
+ * Serving: continuous batching of sampling requests (an extension of the
+ * batched path; the paper's load-balancing view of many small jobs, Sec. 4.2,
+ * applied to requests that arrive over time).  A server owns a device output
+ * arena of `arena_bytes`; a request is admitted (first come, first served)
+ * once its output footprint (8 n bytes) fits in the arena, and every request
+ * admitted while earlier batches are still running joins the next batch,
+ * launched on the next of `n_streams` streams, so batches overlap on the
+ * device.  Each request's output equals dcs_sample_ex /
+ * dcs_sample_replacement_ex with the same arguments, bit for bit, whatever
+ * else shares its batch.
+ *   dcs_server_create: arena_bytes > 0; max_batch >= 1 requests per batch;
+ *     1 <= n_streams <= 8; auto_release != 0 frees a request's arena space
+ *     as soon as it completes (its output may then be overwritten).
+ *   dcs_server_submit: enqueue one request; arrival_s is the scheduled arrival
+ *     time on the dcs_server_now() clock (latency is measured from it; pass a
+ *     negative value for "now").  DCS_EINVAL for an invalid request or one
+ *     larger than the arena.
+ *   dcs_server_submit_schedule: a host thread submits requests[i] at time
+ *     arrival_s[i] (open loop); returns at once.  The arrays are copied.
+ *   dcs_server_poll: state 0 queued, 1 running, 2 done; out_dev (valid once
+ *     done, until released) and latency_s (done only) may be NULL.
+ *   dcs_server_release: frees a done request's arena space.
+ *   dcs_server_drain: blocks until every submitted request is done.
+ *   dcs_server_stats: completed count, samples, p50 / p99 latency (s) and the
+ *     span from first arrival to last completion (s).
+ */
+typedef struct dcs_server dcs_server;
+typedef struct dcs_request {
+  uint64_t n;
+  uint64_t N;
+  uint64_t seed;
+  uint32_t variant; /* 0 = without replacement, 1 = with replacement */
+  uint32_t n0;      /* 0 = default */
+} dcs_request;
+typedef struct dcs_server_stats {
+  uint64_t completed;
+  uint64_t samples;
+  double p50_s;
+  double p99_s;
+  double max_s;
+  double span_s;
+  uint64_t batches;
+} dcs_server_stats;
+int32_t dcs_server_create(uint64_t arena_bytes, uint32_t max_batch, uint32_t n_streams,
+                          int32_t auto_release, dcs_server** server);
+int32_t dcs_server_submit(dcs_server* server, const dcs_request* request, double arrival_s,
+                          uint64_t* ticket);
+int32_t dcs_server_submit_schedule(dcs_server* server, const dcs_request* requests,
+                                   const double* arrival_s, uint64_t count, uint64_t* first_ticket);
+int32_t dcs_server_poll(dcs_server* server, uint64_t ticket, int32_t* state, uint64_t** out_dev,
+                        double* latency_s);
+int32_t dcs_server_release(dcs_server* server, uint64_t ticket);
+/* Copies a done (unreleased) request's n values to dst_dev (device memory,
+ * 8 n bytes), asynchronously on `stream`. */
+int32_t dcs_server_copy_out(dcs_server* server, uint64_t ticket, uint64_t* dst_dev, void* stream);
+int32_t dcs_server_drain(dcs_server* server);
+int32_t dcs_server_stats_read(dcs_server* server, dcs_server_stats* stats);
+int32_t dcs_server_destroy(dcs_server* server);
+double dcs_server_now(void);
+
 /* Waits for `stream`, then reports and clears any error latched by the
  * library's kernels: DCS_EDEVICE if one was latched, else DCS_OK. */
 int32_t dcs_synchronize(void* stream);

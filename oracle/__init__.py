@@ -45,7 +45,13 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
+        _lib = configure(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def configure(L: ctypes.CDLL) -> ctypes.CDLL:
+    """Declare the argument and result types of a loaded oracle library."""
+    if True:
         u64, u32, i32, dbl, flt = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
                                    ctypes.c_double, ctypes.c_float)
         p64 = ctypes.POINTER(ctypes.c_uint64)
@@ -69,6 +75,8 @@ def lib() -> ctypes.CDLL:
             "dcs_ref_lnfact_diff": (dbl, [u64, u64]),
             "dcs_ref_hyp": (u64, [u64, u64, u64, u64, u64]),
             "dcs_ref_bin": (u64, [u64, u64, u64, u64, u64]),
+            "dcs_ref_hyp_mode": (u64, [u64, u64, u64]),
+            "dcs_ref_bin_mode": (u64, [u64, u64, u64]),
             "dcs_ref_tree_stats": (i32, [u64, u64, u64, u32, p64]),
             "dcs_ref_log32_batch": (None, [ctypes.c_void_p, u64, ctypes.c_void_p]),
             "dcs_ref_log64_batch": (None, [ctypes.c_void_p, u64, ctypes.c_void_p]),
@@ -83,8 +91,7 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = L
-    return _lib
+    return L
 
 
 def _p64(a: np.ndarray):
@@ -195,6 +202,14 @@ def lnfact_diff(a: int, b: int) -> float:
 
 def hyp(n: int, M: int, N: int, seed: int, node_id: int) -> int:
     return int(lib().dcs_ref_hyp(n, M, N, seed, node_id))
+
+
+def hyp_mode(n: int, M: int, N: int) -> int:
+    return int(lib().dcs_ref_hyp_mode(n, M, N))
+
+
+def bin_mode(n: int, l: int, Nv: int) -> int:
+    return int(lib().dcs_ref_bin_mode(n, l, Nv))
 
 
 def binom(n: int, l: int, Nv: int, seed: int, node_id: int) -> int:

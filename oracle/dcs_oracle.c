@@ -322,6 +322,16 @@ static uint64_t muldiv_floor(uint64_t x, uint64_t y, uint64_t z) {
   return (uint64_t)(p / z);
 }
 
+/* Mode of Hyp(n, M, N): floor((n+1)(M+1)/(N+2)). */
+static uint64_t hyp_mode(uint64_t n, uint64_t M, uint64_t N) {
+  return muldiv_floor(n + 1, M + 1, N + 2);
+}
+
+/* Mode of Bin(n, l/Nv): floor((n+1) l / Nv). */
+static uint64_t bin_mode(uint64_t n, uint64_t l, uint64_t Nv) {
+  return muldiv_floor(n + 1, l, Nv);
+}
+
 /* Ratio-of-uniforms acceptance loop shared in shape by both distributions
  * (Stadlober 1990): X = a + s (V - 1/2) / U, k = floor(X), accept iff
  * U^2 <= f(k)/f(mode), i.e. 2 ln U <= T(k), with the two squeezes
@@ -362,7 +372,7 @@ static uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, draws_t *dr) {
   double a = mu + 0.5;
   double w = sqrt(var + 0.5);
   double s = REF_D1 * w + REF_D2;
-  uint64_t mode = muldiv_floor(n + 1, M + 1, N + 2);
+  uint64_t mode = hyp_mode(n, M, N);
   double kmax_d = floor(a + 16.0 * w);
   uint64_t kmax = q + 1;
   if (kmax_d < (double)kmax) kmax = (uint64_t)kmax_d;
@@ -428,7 +438,7 @@ static uint64_t bin_core(uint64_t n, uint64_t l, uint64_t Nv, draws_t *dr) {
   double a = mu + 0.5;
   double w = sqrt(var + 0.5);
   double s = REF_D1 * w + REF_D2;
-  uint64_t mode = muldiv_floor(n + 1, l, Nv);
+  uint64_t mode = bin_mode(n, l, Nv);
   double kmax_d = floor(a + 16.0 * w);
   uint64_t kmax = n + 1;
   if (kmax_d < (double)kmax) kmax = (uint64_t)kmax_d;
@@ -805,6 +815,10 @@ EXPORT uint64_t dcs_ref_hyp(uint64_t n, uint64_t M, uint64_t N, uint64_t seed, u
 EXPORT uint64_t dcs_ref_bin(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed, uint64_t id) {
   return bin(n, l, Nv, seed, id);
 }
+/* The modes the ratio-of-uniforms tests are centred on (hypergeometric with
+ * n, M <= N/2; binomial with l <= Nv - l). */
+EXPORT uint64_t dcs_ref_hyp_mode(uint64_t n, uint64_t M, uint64_t N) { return hyp_mode(n, M, N); }
+EXPORT uint64_t dcs_ref_bin_mode(uint64_t n, uint64_t l, uint64_t Nv) { return bin_mode(n, l, Nv); }
 
 /* Tree statistics (for the node-count invariant of Sec. 3.1): counts the
  * internal nodes and the non-empty leaves of the without-replacement tree. */

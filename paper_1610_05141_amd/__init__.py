@@ -14,8 +14,8 @@ from dataclasses import dataclass
 
 __all__ = [
     "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "synchronize",
-    "workspace_size", "bernoulli_capacity_hint", "Batch", "profile_enable", "profile_read",
-    "debug_primitive", "EXPORTED_SYMBOLS", "LIB_PATH",
+    "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
+    "profile_read", "debug_primitive", "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,7 +29,9 @@ EXPORTED_SYMBOLS = (
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
-    "dcs_profile_read", "dcs_debug_primitive",
+    "dcs_profile_read", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
+    "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
+    "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
 )
 
 
@@ -50,6 +52,18 @@ class _Instance(ctypes.Structure):
                 ("out_offset", ctypes.c_uint64), ("variant", ctypes.c_uint32),
                 ("n0", ctypes.c_uint32), ("dense_ratio", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("N", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("variant", ctypes.c_uint32), ("n0", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("samples", ctypes.c_uint64),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("span_s", ctypes.c_double),
+                ("batches", ctypes.c_uint64)]
 
 
 _lib = None
@@ -86,6 +100,18 @@ def lib() -> ctypes.CDLL:
             "dcs_profile_enable": (i32, [i32]),
             "dcs_profile_read": (i32, [i32, ctypes.POINTER(dbl), ctypes.POINTER(u64)]),
             "dcs_debug_primitive": (i32, [i32, vp, vp, vp, u64, u64, u64, u64, u64, vp]),
+            "dcs_server_create": (i32, [u64, u32, u32, i32, ctypes.POINTER(vp)]),
+            "dcs_server_submit": (i32, [vp, ctypes.POINTER(_Request), dbl, ctypes.POINTER(u64)]),
+            "dcs_server_submit_schedule": (i32, [vp, ctypes.POINTER(_Request),
+                                                 ctypes.POINTER(dbl), u64, ctypes.POINTER(u64)]),
+            "dcs_server_poll": (i32, [vp, u64, ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.POINTER(u64)), ctypes.POINTER(dbl)]),
+            "dcs_server_release": (i32, [vp, u64]),
+            "dcs_server_drain": (i32, [vp]),
+            "dcs_server_stats_read": (i32, [vp, ctypes.POINTER(_ServerStats)]),
+            "dcs_server_destroy": (i32, [vp]),
+            "dcs_server_now": (dbl, []),
+            "dcs_server_copy_out": (i32, [vp, u64, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -244,3 +270,82 @@ def debug_primitive(op: int, x, x2, y, p0=0, p1=0, p2=0, p3=0, stream=None) -> N
     rc = lib().dcs_debug_primitive(op, _ptr(x), _ptr(x2), _ptr(y), count, p0, p1, p2, p3,
                                    _stream_handle(stream))
     _check(rc, "dcs_debug_primitive")
+
+
+class Server:
+    """Continuous-batching sampling server (see dcs_server_* in include/dcs.h)."""
+
+    def __init__(self, arena_bytes: int, max_batch: int = 1024, n_streams: int = 4,
+                 auto_release: bool = False):
+        h = ctypes.c_void_p(0)
+        _check(lib().dcs_server_create(arena_bytes, max_batch, n_streams,
+                                       1 if auto_release else 0, ctypes.byref(h)),
+               "dcs_server_create")
+        self._h = h
+
+    @staticmethod
+    def now() -> float:
+        return float(lib().dcs_server_now())
+
+    def submit(self, n: int, N: int, seed: int, variant: int = 0, n0: int = 0,
+               arrival_s: float = -1.0) -> int:
+        tk = ctypes.c_uint64(0)
+        r = _Request(n, N, seed, variant, n0)
+        _check(lib().dcs_server_submit(self._h, ctypes.byref(r), float(arrival_s),
+                                       ctypes.byref(tk)), "dcs_server_submit")
+        return int(tk.value)
+
+    def submit_schedule(self, requests, arrival_s) -> int:
+        """requests: iterable of (n, N, seed[, variant[, n0]]); arrival times on
+        the server clock.  Returns the first ticket; tickets are consecutive."""
+        reqs = list(requests)
+        arr = (_Request * len(reqs))()
+        for i, r in enumerate(reqs):
+            r = tuple(r) + (0,) * (5 - len(r))
+            arr[i] = _Request(*r)
+        times = (ctypes.c_double * len(reqs))(*[float(t) for t in arrival_s])
+        first = ctypes.c_uint64(0)
+        _check(lib().dcs_server_submit_schedule(self._h, arr, times, len(reqs),
+                                                ctypes.byref(first)),
+               "dcs_server_submit_schedule")
+        return int(first.value)
+
+    def poll(self, ticket: int):
+        """(state, device pointer or 0, latency seconds)."""
+        st = ctypes.c_int32(0)
+        ptr = ctypes.POINTER(ctypes.c_uint64)()
+        lat = ctypes.c_double(0)
+        _check(lib().dcs_server_poll(self._h, ticket, ctypes.byref(st), ctypes.byref(ptr),
+                                     ctypes.byref(lat)), "dcs_server_poll")
+        addr = ctypes.cast(ptr, ctypes.c_void_p).value or 0
+        return int(st.value), addr, float(lat.value)
+
+    def result(self, ticket: int, n: int, stream=None):
+        """The request's output copied into a new int64 CUDA tensor."""
+        import torch
+        out = torch.empty(n, dtype=torch.int64, device="cuda")
+        _check(lib().dcs_server_copy_out(self._h, ticket, _ptr(out), _stream_handle(stream)),
+               "dcs_server_copy_out")
+        return out
+
+    def release(self, ticket: int) -> None:
+        _check(lib().dcs_server_release(self._h, ticket), "dcs_server_release")
+
+    def drain(self) -> None:
+        _check(lib().dcs_server_drain(self._h), "dcs_server_drain")
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().dcs_server_stats_read(self._h, ctypes.byref(st)), "dcs_server_stats_read")
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            lib().dcs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

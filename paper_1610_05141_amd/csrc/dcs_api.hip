@@ -15,9 +15,11 @@
 #include <vector>
 
 #include "../../include/dcs.h"
+#include "dcs_host.hpp"
 #include "dcs_kernels.hpp"
 
-namespace {
+namespace dcs {
+namespace host {
 
 using dcs::Control;
 using dcs::Instance;
@@ -41,9 +43,6 @@ uint64_t ceil_div_pow2(uint64_t N, uint32_t d) {
   return (N >> d) + ((N & m) ? 1 : 0);
 }
 
-struct Params {
-  uint32_t n0, dense_ratio;
-};
 
 int32_t read_params(const dcs_params* p, Params* out) {
   out->n0 = kDefaultN0;
@@ -57,16 +56,9 @@ int32_t read_params(const dcs_params* p, Params* out) {
   return DCS_OK;
 }
 
-// Per-instance plan.
-struct Plan {
-  uint32_t cut = 0;
-  uint64_t threads = 0;
-  uint32_t stack_depth = 1;
-  uint64_t leaf_cap = 0;
-};
 
 // variant 0: without replacement, 1: with replacement.
-Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias = 0) {
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias) {
   Plan pl;
   if (n == 0) return pl;
   // Algorithm P cut: depth-`cut` subtrees hold about 2*n0 samples.
@@ -98,10 +90,6 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
   return pl;
 }
 
-// Workspace layout for a tree launch.
-struct TreeLayout {
-  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, total = 0;
-};
 
 TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth) {
   TreeLayout L;
@@ -190,17 +178,6 @@ struct Timing {
   hipEvent_t a, b;
 };
 
-struct DeviceCtx {
-  bool init = false;
-  int cus = 256;
-  int leaf_occupancy = 2;
-  // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
-  // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut
-  int64_t leaf_grid = 0;
-  int32_t cut_bias = 0;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-};
 
 std::mutex g_mu;
 std::vector<DeviceCtx> g_dev;
@@ -266,7 +243,8 @@ void timing_end(hipStream_t s, Timing* t) {
 // Enqueue reset + tree + leaf for the instances already in the workspace.
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t leaf_cap,
-                          uint32_t stack_depth, uint64_t* out, hipStream_t s) {
+                          uint32_t stack_depth, uint64_t* out, hipStream_t s,
+                          bool register_errors) {
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
   Instance* inst = reinterpret_cast<Instance*>(base + L.inst);
@@ -288,9 +266,11 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   e = dcs::launch_leaf(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
-  g_ctl_used.insert(ctl);
+  if (register_errors) g_ctl_used.insert(ctl);
   return DCS_OK;
 }
+
+std::mutex& lock() { return g_mu; }
 
 int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
                     uint64_t* out, void* workspace, size_t ws_bytes, void* stream) {
@@ -325,7 +305,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   I.variant = variant;
   I.cut = pl.cut;
   return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.leaf_cap, pl.stack_depth, out,
-                           static_cast<hipStream_t>(stream));
+                           static_cast<hipStream_t>(stream), true);
 }
 
 struct BernLayout {
@@ -343,7 +323,14 @@ BernLayout bern_layout(uint64_t n_chunks) {
   return L;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dcs
+
+using namespace dcs::host;
+using dcs::Control;
+using dcs::Instance;
+using dcs::Leaf;
+using dcs::Node;
 
 extern "C" {
 
@@ -438,7 +425,7 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
   if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
   if (variant == 0 || variant == 1) {
     if (variant == 0 && n > N) return DCS_EINVAL;
-    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant));
+    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant), 0);
     *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth).total;
     return DCS_OK;
   }
@@ -491,7 +478,7 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
       delete b;
       return DCS_EINVAL;
     }
-    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant);
+    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant, 0);
     Instance I{};
     I.n = d.n;
     I.N = d.N;
@@ -538,7 +525,7 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
   const uint32_t n_inst = static_cast<uint32_t>(b->host.size());
   if (!use_graph || g_profile) {
     return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
-                             b->stack_depth, out_dev, s);
+                             b->stack_depth, out_dev, s, true);
   }
   if (s == nullptr) return DCS_EINVAL;  // capture needs a real stream
   if (b->exec == nullptr || b->graph_out != out_dev) {
@@ -552,7 +539,7 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DCS_EHIP;
     rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
-                           b->stack_depth, out_dev, s);
+                           b->stack_depth, out_dev, s, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != DCS_OK) return rc;

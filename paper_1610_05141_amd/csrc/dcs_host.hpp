@@ -1,0 +1,66 @@
+// dcs_host.hpp -- host-side planning and launch helpers shared by the C ABI
+// implementation (dcs_api.hip) and the serving loop (dcs_server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <set>
+
+#include "../../include/dcs.h"
+#include "dcs_kernels.hpp"
+
+namespace dcs {
+namespace host {
+
+struct Params {
+  uint32_t n0, dense_ratio;
+};
+
+// Validates dcs_params (NULL = defaults).
+int32_t read_params(const dcs_params* p, Params* out);
+
+// Per-instance plan: Algorithm P cut depth, tree threads, DFS stack bound and
+// leaf-job capacity.
+struct Plan {
+  uint32_t cut = 0;
+  uint64_t threads = 0;
+  uint32_t stack_depth = 1;
+  uint64_t leaf_cap = 0;
+};
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias);
+
+// Workspace layout of a tree launch (byte offsets).
+struct TreeLayout {
+  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, total = 0;
+};
+TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth);
+
+struct DeviceCtx {
+  bool init = false;
+  int cus = 256;
+  int leaf_occupancy = 2;
+  // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
+  // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut
+  int64_t leaf_grid = 0;
+  int32_t cut_bias = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+// The library lock (guards the per-device contexts, the latched-error
+// registry and kernel timing).
+std::mutex& lock();
+// Context of the current device (creates it on first use); caller holds lock().
+int32_t device_ctx(DeviceCtx** out);
+// Enqueue reset + tree + leaf on `s` for the instances in the workspace
+// (`single` != NULL: store that one instance first); caller holds lock().
+int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
+                          uint32_t n_inst, uint64_t threads, uint64_t leaf_cap,
+                          uint32_t stack_depth, uint64_t* out, hipStream_t s,
+                          bool register_errors);
+
+}  // namespace host
+}  // namespace dcs

@@ -31,17 +31,35 @@ namespace dcs {
 // Block-wide exclusive prefix sums (one value per thread).  `scratch` holds
 // BLOCK/64 words of LDS; *total receives the block sum.
 // ---------------------------------------------------------------------------
+// Inclusive prefix sum across the 64 lanes of a wave with DPP moves:
+// row_shr 1, 2, 4, 8 inside each 16-lane row, then row_bcast15 / row_bcast31
+// carry the row totals forward (lanes without a source add 0).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_scan_incl(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
 template <int BLOCK, typename T>
 __device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
   constexpr int kW = BLOCK / 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  const T x = wave_scan_incl(v);
   if (lane == 63) scratch[wave] = x;
   __syncthreads();
   T before = 0, all = 0;
@@ -59,6 +77,8 @@ __device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
 __device__ __forceinline__ uint32_t bit_length(uint64_t x) {
   return x == 0 ? 0u : 64u - static_cast<uint32_t>(__clzll(static_cast<long long>(x)));
 }
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void store_out(uint64_t* out, uint64_t v) {
   __builtin_nontemporal_store(v, out);
@@ -332,6 +352,155 @@ __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   write_sorted<B>(out + L.off, L.lo, keys, nv);
 }
 
+// out[i] = base + 1 + vals[i] for i < n with 16-byte stores where the
+// destination allows (out is 8-byte aligned; pairs start at an even index of
+// the destination).
+template <int B>
+__device__ __forceinline__ void write_sorted_pairs(uint64_t* out, uint64_t base,
+                                                   const uint32_t* vals, uint32_t n) {
+  const uint32_t s0 = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 3) & 1u);
+  const uint64_t b1 = base + 1;
+  if (s0 && threadIdx.x == 0 && n > 0) store_out(out, b1 + vals[0]);
+  for (uint32_t e = s0 + 2 * threadIdx.x; e < n; e += 2 * B) {
+    if (e + 1 < n) {
+      u64x2 pr;
+      pr.x = b1 + vals[e];
+      pr.y = b1 + vals[e + 1];
+      __builtin_nontemporal_store(pr, reinterpret_cast<u64x2*>(out + e));
+    } else {
+      store_out(out + e, b1 + vals[e]);
+    }
+  }
+}
+
+// Sparse leaf on a power-of-two range (no word is void): one round of
+// n_v words kept in registers from Philox through the bucket counts; the
+// general round loop takes over only if a value repeats.
+template <int B>
+__device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
+  constexpr int kBlk = kKeys / (4 * B);  // Philox blocks per thread (2 for B=512)
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nv = L.nv;
+  const uint32_t kb = bit_length(L.Nv) - 1;        // range = 2^kb, 1 <= kb <= 32
+  const uint32_t pshift = 32u - kb;                 // value = word >> pshift
+  uint32_t lb = bit_length(nv > 1 ? nv - 1 : 1);
+  lb = lb < 6 ? 6 : (lb > 12 ? 12 : lb);
+  const uint32_t shift = kb > lb ? kb - lb : 0u;
+  const uint32_t nb = 1u << (kb < lb ? kb : lb);
+  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
+  const uint32_t nblk = (nv + 3) >> 2;
+  uint32_t key[4 * kBlk];
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+      const uint4 w = philox_block(st, blk);
+      key[4 * k + 0] = w.x >> pshift;
+      key[4 * k + 1] = w.y >> pshift;
+      key[4 * k + 2] = w.z >> pshift;
+      key[4 * k + 3] = w.w >> pshift;
+    }
+  }
+  uint32_t* cnt = sm.buck;
+  for (uint32_t b = tid; b < bpad(nb); b += B) cnt[b] = 0;
+  if (tid == 0) sm.scr[kScrDups] = 0;
+  __syncthreads();
+  uint32_t slot[4 * kBlk];
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * blk + j < nv) slot[4 * k + j] = atomicAdd(&cnt[bpad(key[4 * k + j] >> shift)], 1u);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the counters: thread tid owns nb/B consecutive ones
+  {
+    const uint32_t per = (nb + B - 1) / B;
+    const uint32_t b0 = tid * per;
+    uint32_t c[kKeys / B];
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kKeys / B; ++k) {
+      c[k] = (k < per && b0 + k < nb) ? cnt[bpad(b0 + k)] : 0u;
+      run += c[k];
+    }
+    uint32_t total;
+    uint32_t acc = block_scan_excl<B, uint32_t>(run, sm.scr, &total);
+#pragma unroll
+    for (uint32_t k = 0; k < kKeys / B; ++k) {
+      if (k < per && b0 + k < nb) {
+        cnt[bpad(b0 + k)] = acc;
+        acc += c[k];
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* tmp = sm.tmp;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (4 * blk + j < nv) {
+          slot[4 * k + j] += cnt[bpad(key[4 * k + j] >> shift)];
+          tmp[slot[4 * k + j]] = key[4 * k + j];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* keys = sm.keys;
+  uint32_t dups = 0;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (4 * blk + j < nv) {
+          const uint32_t x = key[4 * k + j];
+          const uint32_t b = x >> shift;
+          const uint32_t s = cnt[bpad(b)];
+          const uint32_t e = (b + 1 < nb) ? cnt[bpad(b + 1)] : nv;
+          uint32_t lt = 0, eq = 0;
+          if (e - s > 1) {
+            for (uint32_t q = s; q < e; ++q) {
+              const uint32_t y = tmp[q];
+              lt += (y < x) ? 1u : 0u;
+              eq += (y == x && q < slot[4 * k + j]) ? 1u : 0u;
+            }
+          }
+          keys[s + lt + eq] = x;
+          dups += eq ? 1u : 0u;
+        }
+      }
+    }
+  }
+  if (dups) atomicAdd(&sm.scr[kScrDups], dups);
+  __syncthreads();
+  if (sm.scr[kScrDups] != 0) {
+    // a repeated value: continue with the general rounds from this state
+    uint32_t shift2, nb2;
+    bucket_params(L.Nv, nv, &shift2, &nb2);
+    const RangeInfo ri = range_info(L.Nv);
+    uint64_t t = nv;
+    uint32_t have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
+    for (;;) {
+      const uint32_t base = have;
+      t = take_values<B>(st, t, nv - have, ri, sm.scr,
+                         [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
+      const uint32_t d = bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift2, nb2);
+      if (d == 0) break;
+      have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
+    }
+  }
+  write_sorted_pairs<B>(out + L.off, L.lo, keys, nv);
+}
+
 // With-replacement leaf: the first n_v non-void draws, sorted, repeats kept.
 template <int B>
 __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
@@ -507,7 +676,12 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
       L.flags = d.w;
     }
     switch (L.flags & 3u) {
-      case kKindSparse: leaf_sparse<B>(L, out, sm); break;
+      case kKindSparse:
+        if ((L.Nv & (L.Nv - 1)) == 0)
+          leaf_sparse_pow2<B>(L, out, sm);
+        else
+          leaf_sparse<B>(L, out, sm);
+        break;
       case kKindDense: leaf_dense<B>(L, out, sm); break;
       case kKindWr: leaf_wr<B>(L, out, sm); break;
       default: leaf_fill<B>(L, out); break;

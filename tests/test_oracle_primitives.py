@@ -102,6 +102,11 @@ def test_range_map_power_of_two_closed_form(ref):
 def test_range_map_void_rule(ref):
     s = 2**31 + 1  # threshold 2^31 - 1: about half the words are void
     thr = (1 << 32) % s
+    # the words at the boundary: low half of w*s equal to thr (kept) and thr-1 (void)
+    inv = pow(s, -1, 1 << 32)
+    for low, kept in ((thr, True), (thr - 1, False)):
+        w = (low * inv) % (1 << 32)
+        assert (ref.range_map(w, s) >= 0) == kept
     rng = np.random.default_rng(3)
     for w in rng.integers(0, 2**32, size=2000):
         w = int(w)
@@ -145,7 +150,7 @@ def test_log32_matches_mpmath_spot(ref):
 def test_log64_against_mpmath_and_numpy(ref):
     mpmath.mp.dps = 50
     rng = np.random.default_rng(12)
-    x = np.exp(rng.uniform(-700, 700, 400000))
+    x = np.concatenate([np.exp(rng.uniform(-700, 700, 400000)), rng.uniform(0.5, 2.0, 400000)])
     y = ref.log64_batch(x)
     err = np.abs(y - np.log(x)) / np.spacing(np.abs(np.log(x)))
     assert err.max() <= 3.0
@@ -248,6 +253,24 @@ def test_hyp_exact_pmf(ref, n, M, N):
     assert draws.min() >= lo and draws.max() <= hi
     obs = np.bincount(draws - lo, minlength=len(pmf))
     assert _chisq_pvalue(obs, pmf) > 1e-4
+
+
+def test_modes_are_argmax_of_exact_pmf(ref):
+    """The ratio-of-uniforms hat is centred on the mode; it must be a maximiser
+    of the exact pmf (ties included), for every small parameter set."""
+    for N in range(2, 41):
+        for M in range(1, N // 2 + 1):
+            for n in range(1, N // 2 + 1):
+                lo, pmf = _hyp_pmf_exact(n, M, N)
+                m = ref.hyp_mode(n, M, N)
+                assert lo <= m <= lo + len(pmf) - 1
+                assert pmf[m - lo] == max(pmf), (n, M, N, m)
+    for Nv in range(2, 30):
+        for l in range(1, Nv // 2 + 1):
+            for n in range(1, 60):
+                pmf = [math.comb(n, k) * l**k * (Nv - l) ** (n - k) for k in range(n + 1)]
+                m = ref.bin_mode(n, l, Nv)
+                assert pmf[m] == max(pmf), (n, l, Nv, m)
 
 
 def test_hyp_exact_cases(ref):

@@ -132,6 +132,21 @@ def test_window_equals_slice(ref):
     np.testing.assert_array_equal(ref.sample_window(n, N, 1, n - 5, 5), full[-5:])
 
 
+def test_root_split_position_and_stream(ref):
+    """Fig. 1 splits 1..N at floor(N/2) and the left part receives the root's
+    hypergeometric draw: the number of sampled values <= floor(N/2) equals
+    Hyp(n, floor(N/2), N) from the root's stream (node id 1)."""
+    for n, N, seed, n0 in [(5000, 10**6 + 7, 3, 256), (7, 21, 5, 2), (300, 2**33 + 1, 9, 64),
+                           (1 << 16, (1 << 17) + 1, 4, 4096)]:
+        s = ref.sample(n, N, seed, n0=n0)
+        left = int(np.searchsorted(s, N // 2, side="right"))
+        assert left == ref.hyp(n, N // 2, N, seed, 1)
+    for n, N, seed, n0 in [(5000, 10**6 + 7, 3, 256), (9, 5, 2, 2)]:
+        s = ref.replacement(n, N, seed, n0=n0)
+        left = int(np.searchsorted(s, N // 2, side="right"))
+        assert left == ref.binom(n, N // 2, N, seed, 1)
+
+
 def test_tree_size_bound(ref):
     """Sec. 3.1: the recursion tree has at most about 2n/n0 nodes; with
     n_v < n0 leaves and halving splits its internal nodes stay below 2n/n0."""
