@@ -104,6 +104,60 @@ def bench_batched(dcs, reps: int = 3):
     }
 
 
+def bench_other_configs(dcs, reps: int = 5):
+    """Throughput of the other configurations (same timing method: K calls,
+    inputs resident, kernel durations from HIP events on the launch stream)."""
+    import torch
+    res = {}
+    stream = torch.cuda.current_stream()
+    cases = [
+        ("c1_wor_2^20_of_2^32", "wor", (1 << 20, 1 << 32, 1)),
+        ("c2b_wor_dense_2^29_of_2^30", "wor", (1 << 29, 1 << 30, 7)),
+        ("c3a_bernoulli_p0.01_of_2^36", "bern", (0.01, 1 << 36, 7)),
+        ("c3b_wr_2^28_of_2^40", "wr", (1 << 28, 1 << 40, 7)),
+    ]
+    for name, kind, args in cases:
+        if kind == "bern":
+            p, N, seed = args
+            cap = dcs.bernoulli_capacity_hint(p, N)
+            out = torch.empty(cap, dtype=torch.int64, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            run = lambda: dcs.sample_bernoulli(p, N, seed, out=out, capacity=cap, count=cnt,
+                                               stream=stream)
+            kernel = 3
+        else:
+            n, N, seed = args
+            out = torch.empty(n, dtype=torch.int64, device="cuda")
+            f = dcs.sample if kind == "wor" else dcs.sample_replacement
+            run = lambda: f(n, N, seed, out=out, stream=stream)
+            kernel = 2
+        run()
+        dcs.synchronize(stream)
+        dcs.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / reps
+        k_ms, k_n = dcs.profile_read(kernel)
+        t_ms, t_n = dcs.profile_read(1)
+        dcs.profile_enable(False)
+        samples = int(cnt.item()) if kind == "bern" else args[0]
+        k_avg = k_ms / max(k_n, 1)
+        res[name] = {
+            "samples": samples,
+            "ms_per_call": dt * 1e3,
+            "samples_per_s": samples / dt,
+            "dominant_kernel": "k_bern" if kind == "bern" else "k_leaf",
+            "dominant_kernel_ms": k_avg,
+            "dominant_kernel_write_GBs": 8 * samples / (k_avg * 1e-3) / 1e9 if k_avg > 0 else None,
+            "tree_ms": (t_ms / t_n) if t_n else None,
+        }
+        del out
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(dcs, rate: float = 20000.0, warm: int = 10000, timed: int = 100000):
     """Open-loop Poisson arrivals at `rate`/s of instances drawn like the
     batched workload (n capped at 2^24), admitted by output footprint under a
@@ -150,6 +204,7 @@ def main() -> int:
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -232,6 +287,9 @@ def main() -> int:
     }
     del out
     torch.cuda.empty_cache()
+    if not args.no_configs:
+        print("[bench] other configurations", file=sys.stderr, flush=True)
+        rec["configs"] = bench_other_configs(dcs)
     if not args.no_batched:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         rec["batched"] = bench_batched(dcs)

@@ -74,6 +74,10 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
   cut = std::min(cut, kMaxCut);
   pl.cut = cut;
   pl.threads = 1ull << cut;
+  // the top kernel computes the frontier one wave (64 threads, 6 levels)
+  // above the cut, so that each top-level split is computed once per wave
+  pl.top_cut = cut > 6 ? cut - 6 : 0;
+  pl.top_threads = 1ull << pl.top_cut;
   // Deepest possible internal node: its range must reach n0 (without
   // replacement: n_v <= N_v) or 2 (with replacement), or exceed 2^32.
   const uint64_t need_range = variant == 0 ? std::min<uint64_t>(n0, kLeafRange + 1) : 2;
@@ -91,7 +95,8 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
 }
 
 
-TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth) {
+TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth,
+                       uint64_t top_threads) {
   TreeLayout L;
   size_t o = 0;
   L.ctl = o;
@@ -102,6 +107,8 @@ TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uin
   o = align_up(o + sizeof(Leaf) * leaf_cap);
   L.stacks = o;
   o = align_up(o + sizeof(Node) * threads * stack_depth);
+  L.frontier = o;
+  o = align_up(o + sizeof(Node) * std::max<uint64_t>(top_threads, 1));
   L.total = o;
   return L;
 }
@@ -242,21 +249,25 @@ void timing_end(hipStream_t s, Timing* t) {
 
 // Enqueue reset + tree + leaf for the instances already in the workspace.
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
-                          uint32_t n_inst, uint64_t threads, uint64_t leaf_cap,
-                          uint32_t stack_depth, uint64_t* out, hipStream_t s,
+                          uint32_t n_inst, uint64_t threads, uint64_t top_threads,
+                          uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
                           bool register_errors) {
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
   Instance* inst = reinterpret_cast<Instance*>(base + L.inst);
   Leaf* leaves = reinterpret_cast<Leaf*>(base + L.leaves);
   Node* stacks = reinterpret_cast<Node*>(base + L.stacks);
+  Node* frontier = reinterpret_cast<Node*>(base + L.frontier);
   Timing t0{}, t1{}, t2{};
   timing_begin(0, s, &t0);
   hipError_t e = dcs::launch_reset(ctl, single, inst, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   timing_begin(1, s, &t1);
-  e = dcs::launch_tree(inst, n_inst, threads, leaves, leaf_cap, stacks, stack_depth, ctl, s);
+  e = dcs::launch_tree_top(inst, n_inst, top_threads, frontier, leaves, leaf_cap, ctl, s);
+  if (e == hipSuccess)
+    e = dcs::launch_tree(inst, n_inst, threads, frontier, leaves, leaf_cap, stacks, stack_depth,
+                         ctl, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
   uint64_t want = static_cast<uint64_t>(c->cus) * c->leaf_occupancy;
@@ -286,7 +297,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
   const Plan pl = make_plan(n, N, P.n0, variant, c->cut_bias);
-  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth);
+  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
   void* ws = workspace;
   if (ws == nullptr) {
     rc = own_workspace(c, L.total, &ws);
@@ -300,12 +311,14 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   I.seed = seed;
   I.out_offset = 0;
   I.thread_base = 0;
+  I.top_base = 0;
   I.n0 = P.n0;
   I.dense_ratio = P.dense_ratio;
   I.variant = variant;
   I.cut = pl.cut;
-  return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.leaf_cap, pl.stack_depth, out,
-                           static_cast<hipStream_t>(stream), true);
+  I.top_cut = pl.top_cut;
+  return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.top_threads, pl.leaf_cap,
+                           pl.stack_depth, out, static_cast<hipStream_t>(stream), true);
 }
 
 struct BernLayout {
@@ -426,7 +439,7 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
   if (variant == 0 || variant == 1) {
     if (variant == 0 && n > N) return DCS_EINVAL;
     const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant), 0);
-    *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth).total;
+    *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads).total;
     return DCS_OK;
   }
   if (variant == 2) {
@@ -448,7 +461,7 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
 
 struct dcs_batch {
   std::vector<Instance> host;
-  uint64_t threads = 0, leaf_cap = 0, total_out = 0;
+  uint64_t threads = 0, top_threads = 0, leaf_cap = 0, total_out = 0;
   uint32_t stack_depth = 1;
   TreeLayout layout;
   void* ws = nullptr;
@@ -466,7 +479,7 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
   if (batch == nullptr || (count > 0 && instances == nullptr) || count == 0) return DCS_EINVAL;
   *batch = nullptr;
   auto* b = new dcs_batch();
-  uint64_t tb = 0;
+  uint64_t tb = 0, tt = 0;
   for (uint32_t i = 0; i < count; ++i) {
     const dcs_instance& d = instances[i];
     dcs_params pp{sizeof(dcs_params), d.n0, d.dense_ratio, 0};
@@ -485,18 +498,22 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
     I.seed = d.seed;
     I.out_offset = d.out_offset;
     I.thread_base = tb;
+    I.top_base = tt;
     I.n0 = P.n0;
     I.dense_ratio = P.dense_ratio;
     I.variant = d.variant;
     I.cut = pl.cut;
+    I.top_cut = pl.top_cut;
     tb += pl.threads;
+    tt += pl.threads ? pl.top_threads : 0;
     b->leaf_cap += pl.leaf_cap;
     b->stack_depth = std::max(b->stack_depth, pl.stack_depth);
     b->total_out += d.n;
     b->host.push_back(I);
   }
   b->threads = tb;
-  b->layout = tree_layout(count, b->leaf_cap, b->threads, b->stack_depth);
+  b->top_threads = tt;
+  b->layout = tree_layout(count, b->leaf_cap, b->threads, b->stack_depth, b->top_threads);
   if (hipGetDevice(&b->device) != hipSuccess || hipMalloc(&b->ws, b->layout.total) != hipSuccess) {
     delete b;
     return DCS_ENOMEM;
@@ -524,8 +541,8 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
   if (rc) return rc;
   const uint32_t n_inst = static_cast<uint32_t>(b->host.size());
   if (!use_graph || g_profile) {
-    return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
-                             b->stack_depth, out_dev, s, true);
+    return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
+                             b->leaf_cap, b->stack_depth, out_dev, s, true);
   }
   if (s == nullptr) return DCS_EINVAL;  // capture needs a real stream
   if (b->exec == nullptr || b->graph_out != out_dev) {
@@ -538,8 +555,8 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
       b->graph = nullptr;
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DCS_EHIP;
-    rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->leaf_cap,
-                           b->stack_depth, out_dev, s, true);
+    rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
+                           b->leaf_cap, b->stack_depth, out_dev, s, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != DCS_OK) return rc;

@@ -27,6 +27,8 @@ int32_t read_params(const dcs_params* p, Params* out);
 struct Plan {
   uint32_t cut = 0;
   uint64_t threads = 0;
+  uint32_t top_cut = 0;      // frontier depth computed by the top kernel
+  uint64_t top_threads = 0;  // 2^top_cut (0 for an empty instance)
   uint32_t stack_depth = 1;
   uint64_t leaf_cap = 0;
 };
@@ -34,9 +36,10 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
 
 // Workspace layout of a tree launch (byte offsets).
 struct TreeLayout {
-  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, total = 0;
+  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, frontier = 0, total = 0;
 };
-TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth);
+TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth,
+                       uint64_t top_threads);
 
 struct DeviceCtx {
   bool init = false;
@@ -58,8 +61,8 @@ int32_t device_ctx(DeviceCtx** out);
 // Enqueue reset + tree + leaf on `s` for the instances in the workspace
 // (`single` != NULL: store that one instance first); caller holds lock().
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
-                          uint32_t n_inst, uint64_t threads, uint64_t leaf_cap,
-                          uint32_t stack_depth, uint64_t* out, hipStream_t s,
+                          uint32_t n_inst, uint64_t threads, uint64_t top_threads,
+                          uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
                           bool register_errors);
 
 }  // namespace host

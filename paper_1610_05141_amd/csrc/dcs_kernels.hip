@@ -74,6 +74,12 @@ __device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
   return before + x - v;
 }
 
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+  return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
 __device__ __forceinline__ uint32_t bit_length(uint64_t x) {
   return x == 0 ? 0u : 64u - static_cast<uint32_t>(__clzll(static_cast<long long>(x)));
 }
@@ -204,79 +210,120 @@ __device__ uint64_t take_values(const Stream& st, uint64_t t0, uint32_t need, co
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort of keys[0..n) by their top bits (bucket = key >> shift, nb
-// buckets), then exact ranking inside each bucket: keys[] ends ascending
-// with equal values adjacent.  Returns how many entries equal an earlier one.
-// Bucket counters live at padded indices so that the per-thread runs of the
-// counter scan fall in distinct LDS banks.
+// Counting sort by most significant bits (bucket = key >> shift, nb <= 4096
+// buckets), then exact ranking inside shared buckets.  Thread tid holds the
+// keys at positions 4(tid + kB) + j (j < 4) in registers; positions >= n are
+// unused.  Result: sm.keys[0..n) ascending with equal values adjacent;
+// returns how many entries equal an earlier one.  After the counter scan each
+// bucket word holds start | count << 16, so a key alone in its bucket goes
+// straight to its final slot.  Counters sit at padded indices so that the
+// per-thread runs of the scan fall in distinct LDS banks.
 // ---------------------------------------------------------------------------
 template <int B>
-__device__ uint32_t bucket_sort(uint32_t* keys, uint32_t* tmp, uint32_t* buck, uint32_t* scr,
-                                uint32_t n, uint32_t shift, uint32_t nb) {
-  constexpr int R = kKeys / B;
+__device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n, uint32_t shift,
+                                   uint32_t nb, LeafSmem& sm) {
+  constexpr int kBlk = kKeys / (4 * B);
   const uint32_t tid = threadIdx.x;
-  for (uint32_t b = tid; b < bpad(nb); b += B) buck[b] = 0;
-  if (tid == 0) scr[kScrDups] = 0;
+  const uint32_t nblk = (n + 3) >> 2;
+  uint32_t* cnt = sm.buck;
+  for (uint32_t b = tid; b < bpad(nb); b += B) cnt[b] = 0;
+  if (tid == 0) sm.scr[kScrDups] = 0;
   __syncthreads();
-  uint32_t key[R], slot[R], bk[R];
+  uint32_t slot[4 * kBlk];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * B;
-    if (i < n) {
-      key[r] = keys[i];
-      bk[r] = bpad(key[r] >> shift);
-      slot[r] = atomicAdd(&buck[bk[r]], 1u);
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * blk + j < n) slot[4 * k + j] = atomicAdd(&cnt[bpad(key[4 * k + j] >> shift)], 1u);
     }
   }
   __syncthreads();
-  const uint32_t per = (nb + B - 1) / B;
-  const uint32_t b0 = tid * per;
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < per; ++k)
-    if (b0 + k < nb) run += buck[bpad(b0 + k)];
-  uint32_t total;
-  uint32_t acc = block_scan_excl<B, uint32_t>(run, scr, &total);
-  for (uint32_t k = 0; k < per; ++k) {
-    if (b0 + k < nb) {
-      const uint32_t c = buck[bpad(b0 + k)];
-      buck[bpad(b0 + k)] = acc;
-      acc += c;
+  {
+    const uint32_t per = (nb + B - 1) / B;
+    const uint32_t b0 = tid * per;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < per; ++k)
+      if (b0 + k < nb) run += cnt[bpad(b0 + k)];
+    uint32_t total;
+    uint32_t acc = block_scan_excl<B, uint32_t>(run, sm.scr, &total);
+    for (uint32_t k = 0; k < per; ++k) {
+      if (b0 + k < nb) {
+        const uint32_t c = cnt[bpad(b0 + k)];
+        cnt[bpad(b0 + k)] = acc | (c << 16);
+        acc += c;
+      }
     }
   }
   __syncthreads();
+  uint32_t* tmp = sm.tmp;
+  uint32_t* keys = sm.keys;
+  uint32_t shared_keys = 0;  // bit 4k+j: the key shares its bucket
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * B;
-    if (i < n) {
-      slot[r] += buck[bk[r]];  // position in bucket order
-      tmp[slot[r]] = key[r];
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+    if (blk < nblk) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (4 * blk + j < n) {
+          const uint32_t sc = cnt[bpad(key[4 * k + j] >> shift)];
+          const uint32_t s = sc & 0xFFFFu;
+          if ((sc >> 16) == 1) {
+            keys[s] = key[4 * k + j];  // alone in its bucket: final position
+          } else {
+            slot[4 * k + j] += s;      // position in bucket order
+            tmp[slot[4 * k + j]] = key[4 * k + j];
+            shared_keys |= 1u << (4 * k + j);
+          }
+        }
+      }
     }
   }
   __syncthreads();
   uint32_t dups = 0;
+  if (shared_keys) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t i = tid + r * B;
-    if (i < n) {
-      const uint32_t x = key[r];
-      const uint32_t b = x >> shift;
-      const uint32_t s = buck[bpad(b)];
-      const uint32_t e = (b + 1 < nb) ? buck[bpad(b + 1)] : n;
-      uint32_t lt = 0, eq = 0;
-      for (uint32_t j = s; j < e; ++j) {
-        const uint32_t y = tmp[j];
-        lt += (y < x) ? 1u : 0u;
-        eq += (y == x && j < slot[r]) ? 1u : 0u;
+    for (int q = 0; q < 4 * kBlk; ++q) {
+      if (shared_keys & (1u << q)) {
+        const uint32_t x = key[q];
+        const uint32_t sc = cnt[bpad(x >> shift)];
+        const uint32_t s = sc & 0xFFFFu, e = s + (sc >> 16);
+        uint32_t lt = 0, eq = 0;
+        for (uint32_t p = s; p < e; ++p) {
+          const uint32_t y = tmp[p];
+          lt += (y < x) ? 1u : 0u;
+          eq += (y == x && p < slot[q]) ? 1u : 0u;
+        }
+        keys[s + lt + eq] = x;
+        dups += eq ? 1u : 0u;
       }
-      keys[s + lt + eq] = x;
-      dups += eq ? 1u : 0u;
     }
   }
-  if (dups) atomicAdd(&scr[kScrDups], dups);
+  if (dups) atomicAdd(&sm.scr[kScrDups], dups);
   __syncthreads();
-  const uint32_t d = scr[kScrDups];
+  const uint32_t d = sm.scr[kScrDups];
   __syncthreads();
   return d;
+}
+
+// Registers <- keys[0..n) in the layout sort_registers expects.
+template <int B>
+__device__ __forceinline__ void load_registers(uint32_t (&key)[kKeys / B], const uint32_t* keys,
+                                               uint32_t n) {
+  constexpr int kBlk = kKeys / (4 * B);
+  const uint32_t nblk = (n + 3) >> 2;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = threadIdx.x + k * B;
+    if (blk < nblk) {
+      const uint4 v = reinterpret_cast<const uint4*>(keys)[blk];
+      key[4 * k + 0] = v.x;
+      key[4 * k + 1] = v.y;
+      key[4 * k + 2] = v.z;
+      key[4 * k + 3] = v.w;
+    }
+  }
 }
 
 // keys[0..n) ascending with equal values adjacent -> the distinct values in
@@ -328,29 +375,6 @@ __device__ __forceinline__ void bucket_params(uint64_t range, uint32_t n, uint32
   *nb = static_cast<uint32_t>(((range - 1) >> *shift) + 1);
 }
 
-// ---------------------------------------------------------------------------
-// Sparse leaf: Algorithm H semantics, computed in rounds.
-// ---------------------------------------------------------------------------
-template <int B>
-__device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
-  const uint32_t nv = L.nv;
-  const RangeInfo ri = range_info(L.Nv);
-  uint32_t shift, nb;
-  bucket_params(L.Nv, nv, &shift, &nb);
-  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
-  uint32_t* keys = sm.keys;
-  uint32_t have = 0;
-  uint64_t t = 0;
-  for (;;) {
-    const uint32_t base = have;
-    t = take_values<B>(st, t, nv - have, ri, sm.scr,
-                       [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
-    const uint32_t dups = bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
-    if (dups == 0) break;
-    have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
-  }
-  write_sorted<B>(out + L.off, L.lo, keys, nv);
-}
 
 // out[i] = base + 1 + vals[i] for i < n with 16-byte stores where the
 // destination allows (out is 8-byte aligned; pairs start at an even index of
@@ -373,23 +397,54 @@ __device__ __forceinline__ void write_sorted_pairs(uint64_t* out, uint64_t base,
   }
 }
 
-// Sparse leaf on a power-of-two range (no word is void): one round of
-// n_v words kept in registers from Philox through the bucket counts; the
-// general round loop takes over only if a value repeats.
+
+// ---------------------------------------------------------------------------
+// Sparse leaf: Algorithm H semantics, computed in rounds.
+// ---------------------------------------------------------------------------
+// Rounds after the first: keys[0..have) hold distinct values; draw the next
+// (nv - have) non-void values from word t on, sort, repeat while values repeat.
+template <int B>
+__device__ void sparse_rounds(const Stream& st, uint64_t t, uint32_t have, uint32_t nv,
+                              const RangeInfo& ri, uint32_t shift, uint32_t nb, LeafSmem& sm) {
+  uint32_t* keys = sm.keys;
+  uint32_t key[kKeys / B];
+  for (;;) {
+    const uint32_t base = have;
+    t = take_values<B>(st, t, nv - have, ri, sm.scr,
+                       [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
+    load_registers<B>(key, keys, nv);
+    __syncthreads();
+    if (sort_registers<B>(key, nv, shift, nb, sm) == 0) return;
+    have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
+  }
+}
+
+template <int B>
+__device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
+  const uint32_t nv = L.nv;
+  const RangeInfo ri = range_info(L.Nv);
+  uint32_t shift, nb;
+  bucket_params(L.Nv, nv, &shift, &nb);
+  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
+  sparse_rounds<B>(st, 0, 0, nv, ri, shift, nb, sm);
+  write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
+}
+
+// Sparse leaf on a power-of-two range (no word is void): the first round's
+// n_v words go from Philox straight into registers; the general rounds take
+// over only if a value repeats.
 template <int B>
 __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
-  constexpr int kBlk = kKeys / (4 * B);  // Philox blocks per thread (2 for B=512)
+  constexpr int kBlk = kKeys / (4 * B);
   const uint32_t tid = threadIdx.x;
   const uint32_t nv = L.nv;
   const uint32_t kb = bit_length(L.Nv) - 1;        // range = 2^kb, 1 <= kb <= 32
   const uint32_t pshift = 32u - kb;                 // value = word >> pshift
-  uint32_t lb = bit_length(nv > 1 ? nv - 1 : 1);
-  lb = lb < 6 ? 6 : (lb > 12 ? 12 : lb);
-  const uint32_t shift = kb > lb ? kb - lb : 0u;
-  const uint32_t nb = 1u << (kb < lb ? kb : lb);
+  uint32_t shift, nb;
+  bucket_params(L.Nv, nv, &shift, &nb);
   const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
   const uint32_t nblk = (nv + 3) >> 2;
-  uint32_t key[4 * kBlk];
+  uint32_t key[kKeys / B];
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
     const uint32_t blk = tid + k * B;
@@ -401,104 +456,11 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
       key[4 * k + 3] = w.w >> pshift;
     }
   }
-  uint32_t* cnt = sm.buck;
-  for (uint32_t b = tid; b < bpad(nb); b += B) cnt[b] = 0;
-  if (tid == 0) sm.scr[kScrDups] = 0;
-  __syncthreads();
-  uint32_t slot[4 * kBlk];
-#pragma unroll
-  for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
-    if (blk < nblk) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * blk + j < nv) slot[4 * k + j] = atomicAdd(&cnt[bpad(key[4 * k + j] >> shift)], 1u);
-    }
+  if (sort_registers<B>(key, nv, shift, nb, sm) != 0) {
+    const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
+    sparse_rounds<B>(st, nv, have, nv, range_info(L.Nv), shift, nb, sm);
   }
-  __syncthreads();
-  // exclusive scan of the counters: thread tid owns nb/B consecutive ones
-  {
-    const uint32_t per = (nb + B - 1) / B;
-    const uint32_t b0 = tid * per;
-    uint32_t c[kKeys / B];
-    uint32_t run = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kKeys / B; ++k) {
-      c[k] = (k < per && b0 + k < nb) ? cnt[bpad(b0 + k)] : 0u;
-      run += c[k];
-    }
-    uint32_t total;
-    uint32_t acc = block_scan_excl<B, uint32_t>(run, sm.scr, &total);
-#pragma unroll
-    for (uint32_t k = 0; k < kKeys / B; ++k) {
-      if (k < per && b0 + k < nb) {
-        cnt[bpad(b0 + k)] = acc;
-        acc += c[k];
-      }
-    }
-  }
-  __syncthreads();
-  uint32_t* tmp = sm.tmp;
-#pragma unroll
-  for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
-    if (blk < nblk) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (4 * blk + j < nv) {
-          slot[4 * k + j] += cnt[bpad(key[4 * k + j] >> shift)];
-          tmp[slot[4 * k + j]] = key[4 * k + j];
-        }
-      }
-    }
-  }
-  __syncthreads();
-  uint32_t* keys = sm.keys;
-  uint32_t dups = 0;
-#pragma unroll
-  for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
-    if (blk < nblk) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (4 * blk + j < nv) {
-          const uint32_t x = key[4 * k + j];
-          const uint32_t b = x >> shift;
-          const uint32_t s = cnt[bpad(b)];
-          const uint32_t e = (b + 1 < nb) ? cnt[bpad(b + 1)] : nv;
-          uint32_t lt = 0, eq = 0;
-          if (e - s > 1) {
-            for (uint32_t q = s; q < e; ++q) {
-              const uint32_t y = tmp[q];
-              lt += (y < x) ? 1u : 0u;
-              eq += (y == x && q < slot[4 * k + j]) ? 1u : 0u;
-            }
-          }
-          keys[s + lt + eq] = x;
-          dups += eq ? 1u : 0u;
-        }
-      }
-    }
-  }
-  if (dups) atomicAdd(&sm.scr[kScrDups], dups);
-  __syncthreads();
-  if (sm.scr[kScrDups] != 0) {
-    // a repeated value: continue with the general rounds from this state
-    uint32_t shift2, nb2;
-    bucket_params(L.Nv, nv, &shift2, &nb2);
-    const RangeInfo ri = range_info(L.Nv);
-    uint64_t t = nv;
-    uint32_t have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
-    for (;;) {
-      const uint32_t base = have;
-      t = take_values<B>(st, t, nv - have, ri, sm.scr,
-                         [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
-      const uint32_t d = bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift2, nb2);
-      if (d == 0) break;
-      have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
-    }
-  }
-  write_sorted_pairs<B>(out + L.off, L.lo, keys, nv);
+  write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
 
 // With-replacement leaf: the first n_v non-void draws, sorted, repeats kept.
@@ -511,8 +473,11 @@ __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const Stream st = make_stream(L.seed, L.id, kWrLeaf, 0);
   uint32_t* keys = sm.keys;
   take_values<B>(st, 0, nv, ri, sm.scr, [&](uint32_t p, uint32_t v) { keys[p] = v; });
-  bucket_sort<B>(keys, sm.tmp, sm.buck, sm.scr, nv, shift, nb);
-  write_sorted<B>(out + L.off, L.lo, keys, nv);
+  uint32_t key[kKeys / B];
+  load_registers<B>(key, keys, nv);
+  __syncthreads();
+  sort_registers<B>(key, nv, shift, nb, sm);
+  write_sorted_pairs<B>(out + L.off, L.lo, keys, nv);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,6 +639,15 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
       L.seed = static_cast<uint64_t>(d.x) | (static_cast<uint64_t>(d.y) << 32);
       L.nv = d.z;
       L.flags = d.w;
+      // every lane read the same record: make that explicit so the job's
+      // parameters live in scalar registers
+      L.id = uniform64(L.id);
+      L.lo = uniform64(L.lo);
+      L.Nv = uniform64(L.Nv);
+      L.off = uniform64(L.off);
+      L.seed = uniform64(L.seed);
+      L.nv = __builtin_amdgcn_readfirstlane(L.nv);
+      L.flags = __builtin_amdgcn_readfirstlane(L.flags);
     }
     switch (L.flags & 3u) {
       case kKindSparse:
@@ -733,36 +707,69 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
   }
 }
 
-__global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
-                                              uint64_t total_threads, Leaf* leaves,
-                                              uint64_t leaf_cap, Node* stacks,
-                                              uint32_t stack_depth, Control* ctl) {
-  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= total_threads) return;
+__device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t n_inst,
+                                                  uint64_t t, bool top) {
   uint32_t lo = 0, hi = n_inst;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (inst[mid].thread_base <= t) lo = mid; else hi = mid;
+    if ((top ? inst[mid].top_base : inst[mid].thread_base) <= t) lo = mid; else hi = mid;
   }
-  const Instance I = inst[lo];
-  const uint64_t g = t - I.thread_base;
-  Node v{1, 0, I.N, I.n, 0};
-  // Algorithm P: the path to this thread's depth-`cut` node.
-  for (uint32_t d = 0; d < I.cut; ++d) {
-    if (v.nv == 0) return;
+  return lo;
+}
+
+// Walk levels [d0, d1) of Algorithm P from node v along the bits of g (bit
+// d1-1-d chooses the child at depth d).  Returns false when the walk ended
+// early at a leaf or an empty node (the leaf is emitted by the thread whose
+// remaining bits are zero).
+__device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uint64_t g,
+                                          const Instance& I, Leaf* leaves, uint64_t leaf_cap,
+                                          Control* ctl) {
+  for (uint32_t d = d0; d < d1; ++d) {
+    if (v.nv == 0) return false;
     if (is_leaf(v, I)) {
-      const uint32_t below = I.cut - d;
+      const uint32_t below = d1 - d;
       if ((g & ((1ull << below) - 1)) == 0) emit(v, I, leaves, leaf_cap, ctl);
-      return;
+      return false;
     }
     const uint64_t L = split_left(v, I);
     const uint64_t l = v.Nv >> 1;
-    if ((g >> (I.cut - 1 - d)) & 1) {
+    if ((g >> (d1 - 1 - d)) & 1) {
       v = Node{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
     } else {
       v = Node{2 * v.id, v.lo, l, L, v.off};
     }
   }
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ inst,
+                                                  uint32_t n_inst, uint64_t top_threads,
+                                                  Node* frontier, Leaf* leaves, uint64_t leaf_cap,
+                                                  Control* ctl) {
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= top_threads) return;
+  const Instance I = inst[find_instance(inst, n_inst, t, true)];
+  const uint64_t g = t - I.top_base;
+  Node v{1, 0, I.N, I.n, 0};
+  if (!walk_path(v, 0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
+  frontier[t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
+                                              uint64_t total_threads,
+                                              const Node* __restrict__ frontier, Leaf* leaves,
+                                              uint64_t leaf_cap, Node* stacks,
+                                              uint32_t stack_depth, Control* ctl) {
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total_threads) return;
+  const uint32_t ii = find_instance(inst, n_inst, t, false);
+  const Instance I = inst[ii];
+  const uint64_t g = t - I.thread_base;
+  const uint32_t rest = I.cut - I.top_cut;  // levels below the frontier
+  Node v = frontier[I.top_base + (g >> rest)];
+  const uint64_t gl = g & ((1ull << rest) - 1);
+  // Algorithm P: the rest of the path to this thread's depth-`cut` node.
+  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl)) return;
   // Depth-first expansion of the subtree (Algorithm R below depth `cut`).
   Node* stk = stacks + t * stack_depth;
   uint32_t sp = 0;
@@ -1027,13 +1034,23 @@ int leaf_occupancy() {
   return occ;
 }
 
+hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
+                           Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
+                           hipStream_t stream) {
+  if (top_threads == 0) return hipSuccess;
+  const uint64_t blocks = (top_threads + 255) / 256;
+  hipLaunchKernelGGL(k_tree_top, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
+                     n_inst, top_threads, frontier, leaves, leaf_cap, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
-                       Leaf* leaves, uint64_t leaf_cap, Node* stacks, uint32_t stack_depth,
-                       Control* ctl, hipStream_t stream) {
+                       const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
+                       uint32_t stack_depth, Control* ctl, hipStream_t stream) {
   if (total_threads == 0) return hipSuccess;
   const uint64_t blocks = (total_threads + 255) / 256;
   hipLaunchKernelGGL(k_tree, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
-                     n_inst, total_threads, leaves, leaf_cap, stacks, stack_depth, ctl);
+                     n_inst, total_threads, frontier, leaves, leaf_cap, stacks, stack_depth, ctl);
   return hipGetLastError();
 }
 

@@ -14,10 +14,13 @@ struct Instance {
   uint64_t seed;
   uint64_t out_offset;  // first output element of this instance
   uint64_t thread_base; // first tree-kernel thread of this instance
+  uint64_t top_base;    // first top-kernel thread (= its first frontier slot)
   uint32_t n0;
   uint32_t dense_ratio;
   uint32_t variant;     // 0 without replacement, 1 with replacement
   uint32_t cut;         // Algorithm P depth: 2^cut tree threads
+  uint32_t top_cut;     // depth of the frontier the top kernel computes (<= cut)
+  uint32_t pad;
 };
 
 // A recursion-tree node (Fig. 1): node id (root 1, children 2i, 2i+1), the
@@ -73,9 +76,14 @@ hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, h
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream);
 // Resident leaf work-groups per compute unit.
 int leaf_occupancy();
+// Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
+// frontier (written to `frontier`, one slot per top thread).
+hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
+                           Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
+                           hipStream_t stream);
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
-                       Leaf* leaves, uint64_t leaf_cap, Node* stacks, uint32_t stack_depth,
-                       Control* ctl, hipStream_t stream);
+                       const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
+                       uint32_t stack_depth, Control* ctl, hipStream_t stream);
 hipError_t launch_leaf(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
                        uint32_t grid, hipStream_t stream);
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,

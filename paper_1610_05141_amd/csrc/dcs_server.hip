@@ -180,7 +180,7 @@ bool dcs_server::launch_batch() {
   if (batch.empty()) return false;
   // instance table
   std::vector<Instance> inst;
-  uint64_t threads = 0, leaf_cap = 0;
+  uint64_t threads = 0, top_threads = 0, leaf_cap = 0;
   uint32_t stack_depth = 1;
   inst.reserve(batch.size());
   for (uint64_t tk : batch) {
@@ -193,17 +193,20 @@ bool dcs_server::launch_batch() {
     I.seed = R.r.seed;
     I.out_offset = R.off / 8;
     I.thread_base = threads;
+    I.top_base = top_threads;
     I.n0 = n0;
     I.dense_ratio = 16;
     I.variant = R.r.variant;
     I.cut = pl.cut;
+    I.top_cut = pl.top_cut;
     threads += pl.threads;
+    top_threads += pl.threads ? pl.top_threads : 0;
     leaf_cap += pl.leaf_cap;
     stack_depth = std::max(stack_depth, pl.stack_depth);
     inst.push_back(I);
   }
   const uint32_t n_inst = static_cast<uint32_t>(inst.size());
-  const TreeLayout L = dcs::host::tree_layout(n_inst, leaf_cap, threads, stack_depth);
+  const TreeLayout L = dcs::host::tree_layout(n_inst, leaf_cap, threads, stack_depth, top_threads);
   std::lock_guard<std::mutex> lk(dcs::host::lock());
   if (sl->ws_bytes < L.total) {
     if (sl->ws) {
@@ -241,9 +244,9 @@ bool dcs_server::launch_batch() {
     error = DCS_EHIP;
     return false;
   }
-  int32_t rc = dcs::host::run_tree_pipeline(c, sl->ws, L, nullptr, n_inst, threads, leaf_cap,
-                                            stack_depth, reinterpret_cast<uint64_t*>(arena),
-                                            sl->stream, false);
+  int32_t rc = dcs::host::run_tree_pipeline(c, sl->ws, L, nullptr, n_inst, threads, top_threads,
+                                            leaf_cap, stack_depth,
+                                            reinterpret_cast<uint64_t*>(arena), sl->stream, false);
   if (rc == DCS_OK &&
       (hipMemcpyAsync(sl->err, &reinterpret_cast<Control*>(base + L.ctl)->error,
                       sizeof(unsigned int), hipMemcpyDeviceToHost, sl->stream) != hipSuccess ||
