@@ -206,6 +206,7 @@ int32_t device_ctx(DeviceCtx** out) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DCS_EHIP;
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
+    c.bern_occupancy = dcs::bern_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
     if (const char* e = getenv("DCS_CUT_BIAS")) c.cut_bias = atoi(e);
     c.init = true;
@@ -414,7 +415,7 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   const uint32_t grid = static_cast<uint32_t>(
-      std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->leaf_occupancy)));
+      std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->bern_occupancy)));
   const uint32_t lds_cap = 2 * P.n0 + 64;
   timing_begin(3, s, &t1);
   e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,

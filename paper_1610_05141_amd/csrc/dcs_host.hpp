@@ -45,6 +45,7 @@ struct DeviceCtx {
   bool init = false;
   int cus = 256;
   int leaf_occupancy = 2;
+  int bern_occupancy = 2;
   // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
   // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut
   int64_t leaf_grid = 0;

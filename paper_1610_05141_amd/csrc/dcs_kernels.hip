@@ -22,6 +22,8 @@
 //   k_bern       Bernoulli sampling over fixed chunks (Sec. 4.7), chunk
 //                offsets by a decoupled look-back over an atomic ticket.
 //   k_debug      elementwise primitives for bit-exact tests.
+#include <type_traits>
+
 #include "dcs_device.hpp"
 #include "dcs_kernels.hpp"
 
@@ -826,76 +828,151 @@ constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagIncl = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 26;
-constexpr uint32_t kBernLds = kRegionA + kKeys;
+constexpr uint32_t kBernLds = kRegionA;  // holds lds_cap = 2 n0 + 64 <= 8256 offsets
 
-// One pass over the chunk's geometric stream.  Hits i < lds_cap go to pos[]
-// when write == false; when write == true, hits i >= lds_cap are written
-// straight to out (the chunk held more hits than LDS).  Returns the count.
-__device__ uint64_t bern_pass(const Stream& st, uint64_t len, int fp32, double c64, float c32,
+// One pass over the chunk's geometric stream.  Hit k of the chunk sits at
+// 1-based offset q_k = sum_{i<=k} (skip_i + 1); draws are taken in (round,
+// thread, word) order, so each round's offsets come from one block scan.  Hits
+// k < lds_cap go to pos[] when write == false; when write == true, hits
+// k >= lds_cap are written straight to out (the chunk held more hits than LDS).
+// Returns the chunk's hit count.
+//   F32: p >= 2^-10, the chunk has at most 2^22 positions and a skip is at
+//        most 22.2/p < 2^15, so offsets and round sums fit 32 bits.
+//   F64: skips are capped at 2^33 (anything that long ends the chunk).
+template <bool F32>
+__device__ uint64_t bern_pass(const Stream& st, uint64_t len, double c64, float c32,
                               uint32_t* pos, uint32_t lds_cap, bool write, uint64_t* out,
                               uint64_t out_first, uint64_t capacity, uint64_t base,
-                              uint64_t* scr64, uint32_t* scr) {
+                              uint64_t* scr64, uint32_t* scr, uint32_t* ends) {
   constexpr int B = kBernBlock;
+  constexpr uint32_t per = F32 ? 4u : 2u;
+  using Acc = typename std::conditional<F32, uint32_t, uint64_t>::type;
   const uint32_t tid = threadIdx.x;
-  int64_t last = -1;
+  const Acc lim = static_cast<Acc>(len);
+  Acc last = 0;  // offset of the previous round's last draw
   uint64_t count = 0;
-  const uint32_t per = fp32 ? 4u : 2u;
   for (uint32_t blk0 = 0;; blk0 += B) {
     const uint4 w = philox_block(st, blk0 + tid);
-    uint64_t inc[4];
-    uint64_t sum = 0;
-    if (fp32) {
+    Acc inc[per];
+    Acc sum = 0;
+    if constexpr (F32) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        inc[j] = static_cast<uint64_t>(geom_skip32(pick(w, j), c32)) + 1;
+      for (uint32_t j = 0; j < per; ++j) {
+        inc[j] = static_cast<uint32_t>(geom_skip32(pick(w, j), c32)) + 1u;
         sum += inc[j];
       }
     } else {
       const uint64_t d0 = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
       const uint64_t d1 = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (uint32_t j = 0; j < per; ++j) {
         const double g = floor(log64(unit_open0(j ? d1 : d0)) * c64);
-        const double gc = g < 0x1p33 ? g : 0x1p33;  // anything >= 2^33 ends the chunk
+        const double gc = g < 0x1p33 ? g : 0x1p33;
         inc[j] = static_cast<uint64_t>(gc) + 1;
         sum += inc[j];
       }
-      inc[2] = inc[3] = 0;
     }
-    uint64_t total;
-    const uint64_t before = block_scan_excl<B, uint64_t>(sum, scr64, &total);
-    int64_t p = last + static_cast<int64_t>(before);
+    Acc total;
+    Acc q0;
+    if constexpr (F32)
+      q0 = last + block_scan_excl<B, uint32_t>(sum, scr, &total);
+    else
+      q0 = last + block_scan_excl<B, uint64_t>(sum, scr64, &total);
+    Acc q = q0;
+    const bool all_in = last + total <= lim;
+    const uint64_t first_idx = count + per * tid;
     uint32_t in = 0;
+#pragma unroll
     for (uint32_t j = 0; j < per; ++j) {
-      p += static_cast<int64_t>(inc[j]);
-      if (p < static_cast<int64_t>(len)) {
-        const uint64_t idx = count + per * tid + j;
+      q += inc[j];
+      if (q <= lim) {
+        const uint64_t idx = first_idx + j;
         if (!write) {
-          if (idx < lds_cap) pos[idx] = static_cast<uint32_t>(p);
+          if (idx < lds_cap) pos[idx] = static_cast<uint32_t>(q - 1);
         } else if (idx >= lds_cap && out_first + idx < capacity) {
-          store_out(out + out_first + idx, base + static_cast<uint64_t>(p) + 1);
+          store_out(out + out_first + idx, base + static_cast<uint64_t>(q));
         }
         ++in;
       }
     }
-    uint32_t tot_in;
-    block_scan_excl<B, uint32_t>(in, scr, &tot_in);
-    count += tot_in;
-    last += static_cast<int64_t>(total);
-    if (tot_in < per * B) break;
+    if (all_in) {
+      count += per * B;
+      last += total;
+      continue;
+    }
+    // Offsets increase strictly, so exactly one thread starts in range and
+    // holds the chunk's first out-of-range draw; it reports the count.
+    if (in < per && q0 <= lim) *ends = per * tid + in;
+    __syncthreads();
+    count += *ends;
+    __syncthreads();
+    break;
   }
   return count;
 }
 
+// Decoupled look-back (one wave): chunk j's exclusive prefix is the sum of the
+// aggregates of its predecessors back to the nearest one that has published an
+// inclusive prefix.  Each step reads 64 predecessors at once.  Returns the
+// exclusive prefix in every lane; lane 0 publishes j's inclusive prefix.
+// A status word carries its whole message (flag and value in one 64-bit
+// atomic), so relaxed agent-scope atomics suffice; release/acquire would add
+// a write-back and an invalidation of the whole L2 per access.
+__device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64_t cnt,
+                                  Control* ctl) {
+  const uint32_t lane = threadIdx.x & 63;
+  if (j == 0) {
+    if (lane == 0)
+      __hip_atomic_store(&status[0], kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (lane == 0)
+    __hip_atomic_store(&status[j], kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t acc = 0;
+  long long top = static_cast<long long>(j) - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    const long long i = top - static_cast<long long>(lane);
+    // Positions before chunk 0 read as an inclusive prefix of 0.
+    const unsigned long long s =
+        i >= 0 ? __hip_atomic_load(&status[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               : kFlagIncl;
+    const unsigned long long flag = s & ~kValueMask;
+    const unsigned long long incl = __ballot(flag == kFlagIncl);
+    const unsigned long long none = __ballot(flag == 0);
+    const uint32_t first = incl ? static_cast<uint32_t>(__builtin_ctzll(incl)) : 64u;
+    const unsigned long long upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
+    if (none & upto) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicOr(&ctl->error, kErrSpinLimit);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    uint64_t v = lane <= first ? static_cast<uint64_t>(s & kValueMask) : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    acc += v;
+    if (first < 64) break;
+    top -= 64;
+  }
+  if (lane == 0)
+    __hip_atomic_store(&status[j], kFlagIncl | (acc + cnt), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  return acc;
+}
+
+template <bool F32>
 __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
-                                                     uint64_t n_chunks, int fp32, double c64,
-                                                     float c32, unsigned long long* status,
-                                                     uint64_t* out, uint64_t capacity,
-                                                     uint64_t* count_dev, Control* ctl,
-                                                     uint32_t lds_cap) {
+                                                     uint64_t n_chunks, double c64, float c32,
+                                                     unsigned long long* status, uint64_t* out,
+                                                     uint64_t capacity, uint64_t* count_dev,
+                                                     Control* ctl, uint32_t lds_cap) {
   __shared__ uint32_t pos[kBernLds];
   __shared__ uint32_t scr[32];
   __shared__ uint64_t scr64[8];
+  __shared__ uint32_t ends;
   __shared__ unsigned long long cur, excl;
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(&ctl->chunk_ticket, 1ull);
@@ -906,39 +983,16 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
     const uint64_t base = j * chunk;
     const uint64_t len = (N - base) < chunk ? (N - base) : chunk;
     const Stream st = make_stream(seed, j, kBChunk, 0);
-    const uint64_t cnt = bern_pass(st, len, fp32, c64, c32, pos, lds_cap, false, out, 0,
-                                   capacity, base, scr64, scr);
-    if (threadIdx.x == 0) {
-      unsigned long long acc = 0;
-      if (j == 0) {
-        __hip_atomic_store(&status[0], kFlagIncl | cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&status[j], kFlagAgg | cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        long long i = static_cast<long long>(j) - 1;
-        uint32_t spins = 0;
-        while (i >= 0) {
-          const unsigned long long s =
-              __hip_atomic_load(&status[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          const unsigned long long flag = s & ~kValueMask;
-          if (flag == 0) {
-            if (++spins > kSpinLimit) {
-              atomicOr(&ctl->error, kErrSpinLimit);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          acc += s & kValueMask;
-          if (flag == kFlagIncl) break;
-          --i;
+    const uint64_t cnt = bern_pass<F32>(st, len, c64, c32, pos, lds_cap, false, out, 0, capacity,
+                                        base, scr64, scr, &ends);
+    if (threadIdx.x < 64) {
+      const uint64_t acc = bern_lookback(status, j, cnt, ctl);
+      if (threadIdx.x == 0) {
+        excl = acc;
+        if (j == n_chunks - 1) {
+          *count_dev = acc + cnt;
+          ctl->bern_count = acc + cnt;
         }
-        __hip_atomic_store(&status[j], kFlagIncl | (acc + cnt), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      excl = acc;
-      if (j == n_chunks - 1) {
-        *count_dev = acc + cnt;
-        ctl->bern_count = acc + cnt;
       }
     }
     __syncthreads();
@@ -947,7 +1001,8 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
     for (uint64_t i = threadIdx.x; i < held; i += kBernBlock)
       if (first + i < capacity) store_out(out + first + i, base + static_cast<uint64_t>(pos[i]) + 1);
     if (cnt > lds_cap)
-      bern_pass(st, len, fp32, c64, c32, pos, lds_cap, true, out, first, capacity, base, scr64, scr);
+      bern_pass<F32>(st, len, c64, c32, pos, lds_cap, true, out, first, capacity, base, scr64,
+                     scr, &ends);
     __syncthreads();
   }
 }
@@ -1034,6 +1089,15 @@ int leaf_occupancy() {
   return occ;
 }
 
+int bern_occupancy() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_bern<true>), kBernBlock, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 2;
+  return occ;
+}
+
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
                            hipStream_t stream) {
@@ -1066,8 +1130,12 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t* out, uint64_t capacity, uint64_t* count_dev, Control* ctl,
                             uint32_t grid, uint32_t lds_cap, hipStream_t stream) {
   (void)p;
-  hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk, n_chunks,
-                     fp32, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
+  if (fp32)
+    hipLaunchKernelGGL(k_bern<true>, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk,
+                       n_chunks, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
+  else
+    hipLaunchKernelGGL(k_bern<false>, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk,
+                       n_chunks, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
   return hipGetLastError();
 }
 

@@ -76,6 +76,8 @@ hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, h
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream);
 // Resident leaf work-groups per compute unit.
 int leaf_occupancy();
+// Resident Bernoulli work-groups per compute unit.
+int bern_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
 // frontier (written to `frontier`, one slot per top thread).
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,

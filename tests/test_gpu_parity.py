@@ -109,6 +109,30 @@ def test_bernoulli_matches_oracle(ref, p, N, seed):
     assert np.array_equal(got, want), first_mismatch(got, want)
 
 
+# Small n0: chunks clamp to 2^12 positions while only 2 n0 + 64 hits of a
+# chunk stay in LDS, so most chunks take the second (direct-write) pass; the
+# many short chunks also give long look-back chains.
+BERN_N0_CASES = [
+    (0.5, 1 << 22, 11, 2),     # 1024 chunks, ~2048 hits each, 68 held in LDS
+    (0.02, 1 << 24, 12, 16),   # 4096 chunks, ~82 hits each, 96 held in LDS
+    (0.25, 1 << 26, 13, 64),   # 16384 chunks, look-back over many chunks
+    (2.0**-11, 1 << 26, 14, 2),  # double-precision skips, 16384 chunks
+]
+
+
+@pytest.mark.parametrize("p,N,seed,n0", BERN_N0_CASES)
+def test_bernoulli_small_n0_matches_oracle(ref, p, N, seed, n0):
+    m = dcs()
+    announce(f"bernoulli p={p} N={N} seed={seed} n0={n0}")
+    out, cnt = m.sample_bernoulli(p, N, seed, n0=n0)
+    m.synchronize()
+    c = int(cnt.item())
+    want = ref.bernoulli(p, N, seed, n0=n0)
+    assert c == want.size
+    got = to_np_u64(out[:c])
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
 def test_bernoulli_capacity_overflow_keeps_prefix(ref):
     import torch
     m = dcs()
