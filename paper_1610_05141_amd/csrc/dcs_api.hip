@@ -191,8 +191,11 @@ std::vector<DeviceCtx> g_dev;
 std::set<void*> g_ctl_used;  // control blocks to check at synchronize
 bool g_profile = false;
 std::vector<Timing> g_timings;
-double g_prof_ms[4] = {0, 0, 0, 0};
-uint64_t g_prof_n[4] = {0, 0, 0, 0};
+// kinds: 0 reset, 1 tree, 2 leaf stage (both leaf kernels), 3 Bernoulli,
+// 4 leaf kernel of the power-of-two sparse list, 5 leaf kernel of the rest
+constexpr int kProfKinds = 6;
+double g_prof_ms[kProfKinds] = {};
+uint64_t g_prof_n[kProfKinds] = {};
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? DCS_OK : DCS_EHIP; }
 
@@ -253,6 +256,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
                           bool register_errors) {
+  if (leaf_cap >= dcs::kMaxLeafJobs) return DCS_ENOMEM;
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
   Instance* inst = reinterpret_cast<Instance*>(base + L.inst);
@@ -274,8 +278,16 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   uint64_t want = static_cast<uint64_t>(c->cus) * c->leaf_occupancy;
   if (c->leaf_grid > 0) want = static_cast<uint64_t>(c->leaf_grid);
   want = std::max<uint64_t>(1, std::min<uint64_t>(want, leaf_cap));
+  Timing t4{}, t5{};
   timing_begin(2, s, &t2);
-  e = dcs::launch_leaf(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+  timing_begin(4, s, &t4);
+  e = dcs::launch_leaf(true, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+  timing_end(s, &t4);
+  if (e == hipSuccess) {
+    timing_begin(5, s, &t5);
+    e = dcs::launch_leaf(false, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+    timing_end(s, &t5);
+  }
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
   if (register_errors) g_ctl_used.insert(ctl);
@@ -632,7 +644,7 @@ int32_t dcs_profile_enable(int32_t enable) {
     (void)hipEventDestroy(t.b);
   }
   g_timings.clear();
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kProfKinds; ++i) {
     g_prof_ms[i] = 0;
     g_prof_n[i] = 0;
   }
@@ -641,7 +653,7 @@ int32_t dcs_profile_enable(int32_t enable) {
 }
 
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches) {
-  if (kind < 0 || kind > 3 || total_ms == nullptr || launches == nullptr) return DCS_EINVAL;
+  if (kind < 0 || kind >= kProfKinds || total_ms == nullptr || launches == nullptr) return DCS_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   *total_ms = g_prof_ms[kind];
   *launches = g_prof_n[kind];

@@ -67,8 +67,9 @@ __device__ __forceinline__ uint4 philox_block(const Stream& s, uint32_t block) {
     // one 32x32->64 multiply-add each (v_mad_u64_u32) gives both halves
     const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * x0;
     const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * x2;
-    const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ x1 ^ k0;
-    const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ x3 ^ k1;
+    // three-input XOR in one instruction (truth table 0x96 = a ^ b ^ c)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), x1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), x3, k1, 0x96);
     x1 = static_cast<uint32_t>(pb);
     x3 = static_cast<uint32_t>(pa);
     x0 = n0;

@@ -56,7 +56,10 @@ __device__ __forceinline__ uint64_t wave_scan_incl(uint64_t x) {
   return x;
 }
 
-template <int BLOCK, typename T>
+// kTail = false drops the closing barrier that guards `scratch` against the
+// next scan; the caller then guarantees a barrier before scratch is written
+// again.
+template <int BLOCK, typename T, bool kTail = true>
 __device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
   constexpr int kW = BLOCK / 64;
   const int lane = threadIdx.x & 63;
@@ -71,9 +74,19 @@ __device__ __forceinline__ T block_scan_excl(T v, T* scratch, T* total) {
     before += (w < wave) ? s : T(0);
     all += s;
   }
-  __syncthreads();
+  if (kTail) __syncthreads();
   *total = all;
   return before + x - v;
+}
+
+// threadIdx.x, opaque to the optimizer: values derived from it are then
+// recomputed where used instead of being hoisted out of the persistent leaf
+// loop and spilled (a spill reload waits for all of the wave's outstanding
+// output stores).
+__device__ __forceinline__ uint32_t lane_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
@@ -104,16 +117,23 @@ constexpr uint32_t kDenseCap = 2 * kMaxN0 + 64;        // largest accepted n'
 constexpr uint32_t kRegionA = 2 * kMaxN0 + 128;        // >= kDenseCap + 1
 constexpr uint32_t kBuckets = kMaxN0;                  // most buckets used
 constexpr uint32_t kBucketPad = 3;                     // one pad word per 8
-constexpr uint32_t kRegionB = kBuckets + (kBuckets >> kBucketPad);
+// region B ends with spare words: kSpareCount counts keys of unused positions
+constexpr uint32_t kSpareCount = kBuckets + (kBuckets >> kBucketPad);
+constexpr uint32_t kRegionB = kSpareCount + 4;
 constexpr uint32_t kMaskWords = (kDenseCap + 32) / 32 + 1;
 static_assert(kKeys + kMaskWords <= kRegionB, "dense kept values + mask fit region B");
 constexpr uint32_t kCacheLeaves = 32;
 constexpr uint32_t kLeafWords = sizeof(Leaf) / 4;
 constexpr uint32_t kCacheWords = kCacheLeaves * kLeafWords;
 constexpr uint32_t kScratch = 64;
+// sorted keys live in region A's first kKeys words; unused positions scatter
+// to its last word
+constexpr uint32_t kSpareSlot = kRegionA - 1;
+static_assert(kSpareSlot >= kKeys, "spare slot lies outside the sorted keys");
 constexpr uint32_t kSmemWords = kRegionA + kRegionB + kCacheWords + kScratch;
-// scratch words: [0, 16) scan; 16 next-word offset; 17 duplicate count
-constexpr uint32_t kScrNext = 16, kScrDups = 17;
+// scratch words: [0, 16) scan; 16 next-word offset; 17 duplicate flag;
+// [24, 40) per-wave maxima
+constexpr uint32_t kScrNext = 16, kScrDups = 17, kScrMax = 24;
 
 __device__ __forceinline__ uint32_t bpad(uint32_t b) { return b + (b >> kBucketPad); }
 
@@ -212,101 +232,215 @@ __device__ uint64_t take_values(const Stream& st, uint64_t t0, uint32_t need, co
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort by most significant bits (bucket = key >> shift, nb <= 4096
-// buckets), then exact ranking inside shared buckets.  Thread tid holds the
-// keys at positions 4(tid + kB) + j (j < 4) in registers; positions >= n are
-// unused.  Result: sm.keys[0..n) ascending with equal values adjacent;
-// returns how many entries equal an earlier one.  After the counter scan each
-// bucket word holds start | count << 16, so a key alone in its bucket goes
-// straight to its final slot.  Counters sit at padded indices so that the
-// per-thread runs of the scan fall in distinct LDS banks.
+// Batcher's odd-even merge sorting network for 16 inputs (63 comparators):
+// sort both halves, then merge them; two sorted runs interleaved at stride r
+// merge by merging their even and odd subsequences (stride 2r) and then
+// comparing neighbours at distance r.
+// ---------------------------------------------------------------------------
+constexpr uint8_t kNet16[63][2] = {
+    {0, 1},   {2, 3},   {0, 2},   {1, 3},   {1, 2},   {4, 5},   {6, 7},   {4, 6},
+    {5, 7},   {5, 6},   {0, 4},   {2, 6},   {2, 4},   {1, 5},   {3, 7},   {3, 5},
+    {1, 2},   {3, 4},   {5, 6},   {8, 9},   {10, 11}, {8, 10},  {9, 11},  {9, 10},
+    {12, 13}, {14, 15}, {12, 14}, {13, 15}, {13, 14}, {8, 12},  {10, 14}, {10, 12},
+    {9, 13},  {11, 15}, {11, 13}, {9, 10},  {11, 12}, {13, 14}, {0, 8},   {4, 12},
+    {4, 8},   {2, 10},  {6, 14},  {6, 10},  {2, 4},   {6, 8},   {10, 12}, {1, 9},
+    {5, 13},  {5, 9},   {3, 11},  {7, 15},  {7, 11},  {3, 5},   {7, 9},   {11, 13},
+    {1, 2},   {3, 4},   {5, 6},   {7, 8},   {9, 10},  {11, 12}, {13, 14}};
+
+__device__ __forceinline__ void sort16(uint32_t (&v)[16]) {
+#pragma unroll
+  for (int c = 0; c < 63; ++c) {
+    const uint32_t a = v[kNet16[c][0]], b = v[kNet16[c][1]];
+    v[kNet16[c][0]] = min(a, b);
+    v[kNet16[c][1]] = max(a, b);
+  }
+}
+
+// Inclusive prefix maximum across a wave (same DPP pattern, counts >= 0).
+__device__ __forceinline__ uint32_t wave_max_incl(uint32_t x) {
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false)));
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false)));
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false)));
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false)));
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false)));
+  x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false)));
+  return x;
+}
+
+// Sorts the 16-key windows keys[off + 16i .. off + 16i + 16) that start
+// below n (entries past n are 0xFFFFFFFF sentinels).  Returns nonzero in
+// every lane of a wave if one of its windows holds equal neighbours among
+// its first n entries.
+template <int B>
+__device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint32_t off,
+                                                uint32_t tid) {
+  uint64_t dup = 0;
+  const uint32_t w0 = off + 16 * tid;  // 16 B <= kKeys: one window per thread
+  if (w0 < n) {
+    uint4* p = reinterpret_cast<uint4*>(keys + w0);
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 x = p[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+    sort16(v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    const uint32_t lim = n - w0;  // entries of this window below n
+#pragma unroll
+    for (int i = 0; i < 15; ++i) dup |= __ballot(v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
+  }
+  return dup;
+}
+
+// ---------------------------------------------------------------------------
+// Sort of up to 4096 keys held in registers: thread tid holds the keys at
+// positions 4(tid + kB) + j (j < 4); positions >= n are unused.
+//   1. counting pass by most significant bits (bucket = key >> shift,
+//      nb <= 4096 buckets; counters at padded indices so that each thread's
+//      run of the scan falls in distinct LDS banks), LDS atomics give each
+//      key its slot inside its bucket;
+//   2. exclusive scan of the counts (always over 4096 buckets, the unused
+//      ones zero), which also finds the largest bucket c_max;
+//   3. scatter into sm.keys in bucket order;
+//   4. order inside the buckets.  Sorting any window of bucket-ordered keys
+//      only permutes keys within buckets, so sorting the 16-key windows at
+//      16i and then those at 16i + 8 sorts every bucket of at most 9 keys (it
+//      lies inside a window of one of the two passes), and equal keys, which
+//      share a bucket, meet as neighbours inside such a window.  Larger
+//      buckets (c_max > 9, rare) take c_max odd-even transposition rounds
+//      over the whole array -- a pair that spans two buckets never swaps, so
+//      each bucket is sorted after as many rounds as it has keys -- and a
+//      pass comparing neighbours.  With shift = 0 a bucket holds one value:
+//      nothing to order, and values repeat iff c_max >= 2.
+// Result: sm.keys[0..n) ascending, equal values adjacent.  Returns nonzero
+// iff some value occurs twice.  Keys of unused positions add 0 to a spare
+// counter whose scanned start is a spare slot, so the passes carry no
+// per-key branches.  Each key keeps its counter index | slot << 16 in one
+// register between the passes.
 // ---------------------------------------------------------------------------
 template <int B>
 __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n, uint32_t shift,
                                    uint32_t nb, LeafSmem& sm) {
   constexpr int kBlk = kKeys / (4 * B);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t nblk = (n + 3) >> 2;
+  constexpr int kPer = kBuckets / B;  // buckets per thread in the scan
+  constexpr int kPairs = kKeys / (2 * B);
+  static_assert(kPer == 8 && kBuckets % 8 == 0, "scan runs are 8 counters + 1 pad word");
+  (void)nb;
+  const uint32_t tid = lane_tid();
+  const uint32_t wave_first = tid & ~63u;
   uint32_t* cnt = sm.buck;
-  for (uint32_t b = tid; b < bpad(nb); b += B) cnt[b] = 0;
-  if (tid == 0) sm.scr[kScrDups] = 0;
-  __syncthreads();
-  uint32_t slot[4 * kBlk];
-#pragma unroll
-  for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
-    if (blk < nblk) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * blk + j < n) slot[4 * k + j] = atomicAdd(&cnt[bpad(key[4 * k + j] >> shift)], 1u);
-    }
-  }
-  __syncthreads();
-  {
-    const uint32_t per = (nb + B - 1) / B;
-    const uint32_t b0 = tid * per;
-    uint32_t run = 0;
-    for (uint32_t k = 0; k < per; ++k)
-      if (b0 + k < nb) run += cnt[bpad(b0 + k)];
-    uint32_t total;
-    uint32_t acc = block_scan_excl<B, uint32_t>(run, sm.scr, &total);
-    for (uint32_t k = 0; k < per; ++k) {
-      if (b0 + k < nb) {
-        const uint32_t c = cnt[bpad(b0 + k)];
-        cnt[bpad(b0 + k)] = acc | (c << 16);
-        acc += c;
-      }
-    }
-  }
-  __syncthreads();
-  uint32_t* tmp = sm.tmp;
   uint32_t* keys = sm.keys;
-  uint32_t shared_keys = 0;  // bit 4k+j: the key shares its bucket
+  // 1. zero the counters, sentinels after the keys, count
+  for (uint32_t w = tid; w < kSpareCount / 4; w += B)
+    reinterpret_cast<uint4*>(cnt)[w] = make_uint4(0, 0, 0, 0);
+  if (tid < 24) keys[n + tid] = 0xFFFFFFFFu;
+  if (tid == 0) {
+    sm.scr[kScrDups] = 0;
+    cnt[kSpareCount] = 0;
+  }
+  __syncthreads();
+  uint32_t as[4 * kBlk];
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
-    if (blk < nblk) {
+    const uint32_t first = 4 * (wave_first + k * B);  // first key position of the wave
+    if (first + 256 <= n) {                           // every lane holds 4 keys
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (4 * blk + j < n) {
-          const uint32_t sc = cnt[bpad(key[4 * k + j] >> shift)];
-          const uint32_t s = sc & 0xFFFFu;
-          if ((sc >> 16) == 1) {
-            keys[s] = key[4 * k + j];  // alone in its bucket: final position
-          } else {
-            slot[4 * k + j] += s;      // position in bucket order
-            tmp[slot[4 * k + j]] = key[4 * k + j];
-            shared_keys |= 1u << (4 * k + j);
-          }
-        }
+        const int q = 4 * k + j;
+        const uint32_t a = bpad(key[q] >> shift);
+        as[q] = a | (atomicAdd(&cnt[a], 1u) << 16);
       }
-    }
-  }
-  __syncthreads();
-  uint32_t dups = 0;
-  if (shared_keys) {
+    } else if (first < n) {
 #pragma unroll
-    for (int q = 0; q < 4 * kBlk; ++q) {
-      if (shared_keys & (1u << q)) {
-        const uint32_t x = key[q];
-        const uint32_t sc = cnt[bpad(x >> shift)];
-        const uint32_t s = sc & 0xFFFFu, e = s + (sc >> 16);
-        uint32_t lt = 0, eq = 0;
-        for (uint32_t p = s; p < e; ++p) {
-          const uint32_t y = tmp[p];
-          lt += (y < x) ? 1u : 0u;
-          eq += (y == x && p < slot[q]) ? 1u : 0u;
-        }
-        keys[s + lt + eq] = x;
-        dups += eq ? 1u : 0u;
+      for (int j = 0; j < 4; ++j) {
+        const int q = 4 * k + j;
+        const bool live = 4 * (tid + k * B) + j < n;
+        const uint32_t a = live ? bpad(key[q] >> shift) : kSpareCount;
+        as[q] = a | (atomicAdd(&cnt[a], live ? 1u : 0u) << 16);
       }
     }
   }
-  if (dups) atomicAdd(&sm.scr[kScrDups], dups);
   __syncthreads();
-  const uint32_t d = sm.scr[kScrDups];
+  // 2. scan: thread tid owns buckets [8 tid, 8 tid + 8) at words 9 tid ..
+  {
+    uint32_t* run8 = cnt + 9 * tid;
+    uint32_t c[kPer];
+    uint32_t run = 0, big = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      c[k] = run8[k];
+      run += c[k];
+      big = max(big, c[k]);
+    }
+    big = wave_max_incl(big);
+    if ((tid & 63) == 63) sm.scr[kScrMax + (tid >> 6)] = big;
+    uint32_t total;
+    uint32_t acc = block_scan_excl<B, uint32_t, false>(run, sm.scr, &total);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      run8[k] = acc;
+      acc += c[k];
+    }
+    if (tid == 0) cnt[kSpareCount] = kSpareSlot;
+  }
   __syncthreads();
-  return d;
+  uint32_t cmax = 0;
+#pragma unroll
+  for (int w = 0; w < B / 64; ++w) cmax = max(cmax, sm.scr[kScrMax + w]);
+  // 3. scatter in bucket order (unused positions land on the spare slot)
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    if (4 * (wave_first + k * B) < n) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = 4 * k + j;
+        keys[cnt[as[q] & 0xFFFFu] + (as[q] >> 16)] = key[q];
+      }
+    }
+  }
+  __syncthreads();
+  // 4. order inside buckets
+  if (shift == 0) return cmax >= 2 ? 1u : 0u;
+  if (cmax <= 1) return 0u;
+  if (cmax <= 9) {
+    uint64_t dup = window_pass<B>(keys, n, 0, tid);
+    __syncthreads();
+    dup |= window_pass<B>(keys, n, 8, tid);
+    if (dup && (tid & 63) == 0) sm.scr[kScrDups] = 1;
+    __syncthreads();
+    return sm.scr[kScrDups];
+  }
+  for (uint32_t r = 0; r < cmax; ++r) {
+    const uint32_t odd = r & 1u;
+#pragma unroll
+    for (int m = 0; m < kPairs; ++m) {
+      const uint32_t i = 2 * (tid + m * B) + odd;
+      if (i + 1 < n) {
+        const uint32_t a = keys[i], b = keys[i + 1];
+        keys[i] = min(a, b);
+        keys[i + 1] = max(a, b);
+      }
+    }
+    __syncthreads();
+  }
+  uint32_t dup = 0;
+#pragma unroll
+  for (int m = 0; m < kPairs; ++m) {
+    const uint32_t i = 2 * (tid + m * B);
+    if (i + 1 < n) {
+      const uint32_t a = keys[i], b = keys[i + 1];
+      dup |= a == b ? 1u : 0u;
+      if (i + 2 < n) dup |= b == keys[i + 2] ? 1u : 0u;
+    }
+  }
+  if (dup) sm.scr[kScrDups] = 1;
+  __syncthreads();
+  return sm.scr[kScrDups];
 }
 
 // Registers <- keys[0..n) in the layout sort_registers expects.
@@ -366,13 +500,13 @@ __device__ __forceinline__ void write_sorted(uint64_t* out, uint64_t base, const
     store_out(out + i, base + 1 + static_cast<uint64_t>(vals[i]));
 }
 
-// Buckets for keys < range, about n keys: 2^lb buckets, lb = bits of n,
-// clamped to [6, 12].
+// Buckets for keys < range: the top 12 of the key's kb = bits(range - 1)
+// bits (all of them when kb <= 12), at most 4096 buckets.
 __device__ __forceinline__ void bucket_params(uint64_t range, uint32_t n, uint32_t* shift,
                                               uint32_t* nb) {
+  (void)n;
   const uint32_t kb = bit_length(range - 1);
-  uint32_t lb = bit_length(n > 1 ? n - 1 : 1);
-  lb = lb < 6 ? 6 : (lb > 12 ? 12 : lb);
+  constexpr uint32_t lb = 12;
   *shift = kb > lb ? kb - lb : 0u;
   *nb = static_cast<uint32_t>(((range - 1) >> *shift) + 1);
 }
@@ -386,8 +520,9 @@ __device__ __forceinline__ void write_sorted_pairs(uint64_t* out, uint64_t base,
                                                    const uint32_t* vals, uint32_t n) {
   const uint32_t s0 = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 3) & 1u);
   const uint64_t b1 = base + 1;
-  if (s0 && threadIdx.x == 0 && n > 0) store_out(out, b1 + vals[0]);
-  for (uint32_t e = s0 + 2 * threadIdx.x; e < n; e += 2 * B) {
+  const uint32_t tid = lane_tid();
+  if (s0 && tid == 0 && n > 0) store_out(out, b1 + vals[0]);
+  for (uint32_t e = s0 + 2 * tid; e < n; e += 2 * B) {
     if (e + 1 < n) {
       u64x2 pr;
       pr.x = b1 + vals[e];
@@ -438,7 +573,7 @@ __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
 template <int B>
 __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   constexpr int kBlk = kKeys / (4 * B);
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = lane_tid();
   const uint32_t nv = L.nv;
   const uint32_t kb = bit_length(L.Nv) - 1;        // range = 2^kb, 1 <= kb <= 32
   const uint32_t pshift = 32u - kb;                 // value = word >> pshift
@@ -449,7 +584,7 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   uint32_t key[kKeys / B];
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
-    const uint32_t blk = tid + k * B;
+    const uint32_t blk = tid + k * B;  // tid is opaque: no Philox round is hoisted
     if (blk < nblk) {
       const uint4 w = philox_block(st, blk);
       key[4 * k + 0] = w.x >> pshift;
@@ -598,9 +733,14 @@ __device__ void leaf_fill(const Leaf& L, uint64_t* out) {
   for (uint32_t i = threadIdx.x; i < L.nv; i += B) store_out(o + i, L.lo + 1);
 }
 
-template <int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
-                                            uint64_t* out, const Control* ctl) {
+// Persistent leaf loop: job i of the class's list goes to work-group
+// i mod G, whose job records are read kCacheLeaves at a time into LDS.
+// kPow2: the front list (sparse leaves over power-of-two ranges) with only
+// that leaf body compiled in, so that the hot path keeps its values in
+// registers; otherwise the back list with every other leaf body.
+template <int B, bool kPow2>
+__device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
+                                          uint64_t* out, Control* ctl) {
   __shared__ uint32_t smem[kSmemWords];
   LeafSmem sm;
   sm.keys = smem;
@@ -610,8 +750,15 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
   sm.mask = sm.buck + kKeys;
   uint32_t* cache = smem + kRegionA + kRegionB;
   sm.scr = cache + kCacheWords;
-  const unsigned long long cnt = ctl->leaf_count;
-  const uint64_t n_leaves = cnt < leaf_cap ? cnt : leaf_cap;
+  const unsigned long long counts = ctl->leaf_counts;
+  const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
+  if (front + back > leaf_cap) {
+    // the lists overlap (or one overflowed): the tree kernel flagged or
+    // would have flagged capacity; report it and sample nothing
+    if (!kPow2 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->error, kErrLeafCapacity);
+    return;
+  }
+  const uint64_t n_leaves = kPow2 ? front : back;
   const uint64_t G = gridDim.x;
   for (uint64_t j = 0;; ++j) {
     const uint64_t i = blockIdx.x + j * G;
@@ -624,7 +771,8 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
         const uint32_t which = tid / 3, part = tid % 3;
         const uint64_t li = i + static_cast<uint64_t>(which) * G;
         if (li < n_leaves) {
-          const uint4 v = reinterpret_cast<const uint4*>(leaves + li)[part];
+          const Leaf* rec = kPow2 ? leaves + li : leaves + (leaf_cap - 1 - li);
+          const uint4 v = reinterpret_cast<const uint4*>(rec)[part];
           reinterpret_cast<uint4*>(cache + which * kLeafWords)[part] = v;
         }
       }
@@ -651,19 +799,30 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
       L.nv = __builtin_amdgcn_readfirstlane(L.nv);
       L.flags = __builtin_amdgcn_readfirstlane(L.flags);
     }
-    switch (L.flags & 3u) {
-      case kKindSparse:
-        if ((L.Nv & (L.Nv - 1)) == 0)
-          leaf_sparse_pow2<B>(L, out, sm);
-        else
-          leaf_sparse<B>(L, out, sm);
-        break;
-      case kKindDense: leaf_dense<B>(L, out, sm); break;
-      case kKindWr: leaf_wr<B>(L, out, sm); break;
-      default: leaf_fill<B>(L, out); break;
+    if constexpr (kPow2) {
+      leaf_sparse_pow2<B>(L, out, sm);
+    } else {
+      switch (L.flags & 3u) {
+        case kKindSparse: leaf_sparse<B>(L, out, sm); break;
+        case kKindDense: leaf_dense<B>(L, out, sm); break;
+        case kKindWr: leaf_wr<B>(L, out, sm); break;
+        default: leaf_fill<B>(L, out); break;
+      }
     }
     __syncthreads();
   }
+}
+
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_pow2(
+    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl) {
+  leaf_loop<B, true>(leaves, leaf_cap, out, ctl);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_mixed(
+    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl) {
+  leaf_loop<B, false>(leaves, leaf_cap, out, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,13 +848,21 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
     kind = static_cast<uint64_t>(I.dense_ratio) * v.nv >= v.Nv ? kKindDense : kKindSparse;
   uint64_t pieces = 1;
   if (kind == kKindFill && v.nv > kFillPiece) pieces = (v.nv + kFillPiece - 1) / kFillPiece;
-  const unsigned long long base =
-      atomicAdd(&ctl->leaf_count, static_cast<unsigned long long>(pieces));
+  // sparse leaves over a power-of-two range fill the job array from the
+  // front, everything else from the back; the leaf kernel of the other class
+  // reports the two lists meeting
+  const bool front = kind == kKindSparse && (v.Nv & (v.Nv - 1)) == 0;
+  // one counter word at a uniform address, so that the compiler combines
+  // the wave's increments into a single atomic
+  const unsigned long long old =
+      atomicAdd(&ctl->leaf_counts, front ? 1ull : static_cast<unsigned long long>(pieces) << 32);
+  const uint64_t base = front ? (old & 0xFFFFFFFFull) : (old >> 32);
   for (uint64_t j = 0; j < pieces; ++j) {
     if (base + j >= cap) {
       atomicOr(&ctl->error, kErrLeafCapacity);
       return;
     }
+    const uint64_t at = front ? base + j : cap - 1 - (base + j);
     Leaf L;
     L.id = v.id;
     L.lo = v.lo;
@@ -705,7 +872,7 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
     L.nv = static_cast<uint32_t>(pieces == 1 ? v.nv
                                              : ((j + 1 < pieces) ? kFillPiece : v.nv - j * kFillPiece));
     L.flags = kind | (I.n0 << 8);
-    leaves[base + j] = L;
+    leaves[at] = L;
   }
 }
 
@@ -801,8 +968,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
 
 __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table) {
   if (threadIdx.x == 0) {
-    ctl->leaf_count = 0;
-    ctl->leaf_ticket = 0;
+    ctl->leaf_counts = 0;
     ctl->chunk_ticket = 0;
     ctl->bern_count = 0;
     if (has_single) table[0] = single;
@@ -814,8 +980,7 @@ __global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n) {
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     status[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->leaf_count = 0;
-    ctl->leaf_ticket = 0;
+    ctl->leaf_counts = 0;
     ctl->chunk_ticket = 0;
     ctl->bern_count = 0;
   }
@@ -1083,7 +1248,7 @@ hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hip
 int leaf_occupancy() {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &occ, reinterpret_cast<const void*>(k_leaf<kLeafBlock>), kLeafBlock, 0) != hipSuccess ||
+          &occ, reinterpret_cast<const void*>(k_leaf_mixed<kLeafBlock>), kLeafBlock, 0) != hipSuccess ||
       occ <= 0)
     occ = 2;
   return occ;
@@ -1118,10 +1283,14 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
-                       uint32_t grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_leaf<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves, leaf_cap,
-                     out, ctl);
+hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
+                       Control* ctl, uint32_t grid, hipStream_t stream) {
+  if (pow2_list)
+    hipLaunchKernelGGL(k_leaf_pow2<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
+                       leaf_cap, out, ctl);
+  else
+    hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
+                       leaf_cap, out, ctl);
   return hipGetLastError();
 }
 

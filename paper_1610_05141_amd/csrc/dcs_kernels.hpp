@@ -49,8 +49,12 @@ constexpr uint32_t kKindFill = 3;    // with replacement, N_v = 1: constant
 
 // Control block at the start of a workspace.
 struct Control {
-  unsigned long long leaf_count;   // leaves appended by the tree kernel
-  unsigned long long leaf_ticket;  // next leaf to hand out in the leaf kernel
+  // leaf jobs appended by the tree kernels: low 32 bits count the sparse
+  // leaves over power-of-two ranges (filled from the front of the job array),
+  // high 32 bits all others (filled from the back); one 64-bit atomic
+  // serves both
+  unsigned long long leaf_counts;
+  unsigned long long pad0;
   unsigned long long chunk_ticket; // Bernoulli: next chunk to hand out
   unsigned int error;              // latched error bits (kErr*)
   unsigned int pad;
@@ -62,6 +66,7 @@ constexpr unsigned kErrStackDepth = 2u;     // tree deeper than the planned stac
 constexpr unsigned kErrSpinLimit = 4u;      // Bernoulli look-back waited too long
 constexpr unsigned kErrLeafTooLarge = 8u;   // a leaf exceeds the kernel's LDS bound
 
+constexpr uint64_t kMaxLeafJobs = 1ull << 31;  // keeps the two halves of leaf_counts apart
 constexpr int kLeafBlock = 512;             // threads of a leaf work-group
 constexpr int kBernBlock = 256;             // threads of a Bernoulli work-group
 constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
@@ -86,8 +91,10 @@ hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_t
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
                        uint32_t stack_depth, Control* ctl, hipStream_t stream);
-hipError_t launch_leaf(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
-                       uint32_t grid, hipStream_t stream);
+// Leaf kernel over one of the two job lists: pow2_list = the front list
+// (sparse leaves over power-of-two ranges), else the back list (all others).
+hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
+                       Control* ctl, uint32_t grid, hipStream_t stream);
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,

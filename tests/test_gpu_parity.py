@@ -70,6 +70,8 @@ WR_CASES = [
     (5, 3, 1, 2),
     (1 << 16, 1 << 10, 8, 4096),     # many repeats per value
     (3000, 2**45 + 1, 9, 4096),
+    (4000, 8, 12, 4096),             # one leaf, 8 values: buckets of ~500 equal keys
+    (4095, 5, 13, 4096),
 ]
 
 
