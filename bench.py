@@ -89,11 +89,14 @@ def bench_batched(dcs, reps: int = 3):
     [1e-6, 0.5], seeds 0..4095): one hipGraph-replayed batch vs one plain
     dcs_sample call per instance on one stream (synchronized once)."""
     import torch
+    from paper_1610_05141_amd import autotune
     from paper_1610_05141_amd.workloads import batched_instances
     insts = batched_instances(4096)
+    table = autotune.load_table()
     specs, off = [], 0
     for x in insts:
-        specs.append(dcs.InstanceSpec(n=x.n, N=x.N, seed=x.seed, out_offset=off))
+        n0 = autotune.n0_for(x.n, x.N, table)  # the autotuner's recorded leaf size
+        specs.append(dcs.InstanceSpec(n=x.n, N=x.N, seed=x.seed, out_offset=off, n0=n0))
         off += x.n
     total = off
     out = torch.empty(total, dtype=torch.int64, device="cuda")
@@ -111,12 +114,14 @@ def bench_batched(dcs, reps: int = 3):
     # plain: one call per instance into the same buffer
     with torch.cuda.stream(stream):
         for s_, x in zip(specs, insts):
-            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream)
+            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream,
+                       n0=s_.n0)
     dcs.synchronize(stream)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for s_, x in zip(specs, insts):
-            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream)
+            dcs.sample(x.n, x.N, x.seed, out=out[s_.out_offset:s_.out_offset + x.n], stream=stream,
+                       n0=s_.n0)
     dcs.synchronize(stream)
     plain_s = time.perf_counter() - t0
     b.close()
@@ -130,6 +135,9 @@ def bench_batched(dcs, reps: int = 3):
         "batched_samples_per_s": total / batched_s,
         "plain_ms": plain_s * 1e3,
         "speedup_vs_plain": plain_s / batched_s,
+        "leaf_sizes": {str(k): sum(1 for s_ in specs if s_.n0 == k)
+                       for k in sorted({s_.n0 for s_ in specs})},
+        "tuning_table": "paper_1610_05141_amd/tune_table.json" if table else None,
     }
 
 
@@ -158,13 +166,13 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
             cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
             run = lambda: dcs.sample_bernoulli(p, N, seed, out=out, capacity=cap, count=cnt,
                                                stream=stream)
-            kernel = 3
+            kernels = {"k_bern": 3}
         else:
             n, N, seed = args
             out = torch.empty(n, dtype=torch.int64, device="cuda")
             f = dcs.sample if kind == "wor" else dcs.sample_replacement
             run = lambda: f(n, N, seed, out=out, stream=stream)
-            kernel = 2
+            kernels = {"k_leaf_pow2": 4, "k_leaf_mixed": 5}
         run()
         dcs.synchronize(stream)
         dcs.profile_enable(True)
@@ -173,17 +181,22 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
             run()
         dcs.synchronize(stream)
         dt = (time.perf_counter() - t0) / reps
-        k_ms, k_n = dcs.profile_read(kernel)
+        avgs = {}
+        for kname, kind_id in kernels.items():
+            k_ms, k_n = dcs.profile_read(kind_id)
+            avgs[kname] = k_ms / max(k_n, 1)
         t_ms, t_n = dcs.profile_read(1)
         dcs.profile_enable(False)
         samples = int(cnt.item()) if kind == "bern" else args[0]
-        k_avg = k_ms / max(k_n, 1)
+        dom = max(avgs, key=avgs.get)
+        k_avg = avgs[dom]
         res[name] = {
             "samples": samples,
             "ms_per_call": dt * 1e3,
             "samples_per_s": samples / dt,
-            "dominant_kernel": "k_bern" if kind == "bern" else "k_leaf",
+            "dominant_kernel": dom,
             "dominant_kernel_ms": k_avg,
+            "kernels_ms": avgs,
             "dominant_kernel_write_GBs": 8 * samples / (k_avg * 1e-3) / 1e9 if k_avg > 0 else None,
             "tree_ms": (t_ms / t_n) if t_n else None,
         }
@@ -281,7 +294,9 @@ def main() -> int:
     dcs.synchronize(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    leaf_ms, leaf_n = dcs.profile_read(2)
+    stage_ms, stage_n = dcs.profile_read(2)
+    leaf_ms, leaf_n = dcs.profile_read(4)     # the power-of-two sparse leaf kernel
+    mixed_ms, mixed_n = dcs.profile_read(5)   # leaf kernel of the other leaf kinds
     tree_ms, tree_n = dcs.profile_read(1)
     reset_ms, reset_n = dcs.profile_read(0)
     dcs.profile_enable(False)
@@ -319,12 +334,15 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": recorded_traffic(),
-            "kernel": "k_leaf",
+            "kernel": "k_leaf_pow2",
             "kernel_avg_ms": leaf_avg_ms,
         },
+        "geometry": {"cut_bias,leaf_wgs_per_cu": list(dcs.tune_get(0, 30))},
         "kernels_ms_per_step": {"reset": reset_ms / max(reset_n, 1),
                                 "tree": tree_ms / max(tree_n, 1),
-                                "leaf": leaf_avg_ms},
+                                "k_leaf_pow2": leaf_avg_ms,
+                                "k_leaf_mixed": mixed_ms / max(mixed_n, 1),
+                                "leaf_stage": stage_ms / max(stage_n, 1)},
         "whole_step_write_GBs": BYTES_PER_SAMPLE * N_SAMPLE / (ms_per_step * 1e-3) / 1e9,
         "invariants_ok": props_ok,
     }

@@ -214,6 +214,27 @@ double dcs_server_now(void);
  * library's kernels: DCS_EDEVICE if one was latched, else DCS_OK. */
 int32_t dcs_synchronize(void* stream);
 
+/*
+ * Launch-geometry tuning (Sec. 4.2's load balancing is static here: the
+ * geometry decides how the tree and the leaf jobs are spread over the GPU).
+ * A size class is (variant: 0 without, 1 with replacement; log2_n =
+ * floor(log2 n), 0..63).  cut_bias is added to the depth at which the tree
+ * kernels hand subtrees to threads (2^cut threads per instance);
+ * leaf_wgs_per_cu is the number of leaf work-groups per compute unit (0 =
+ * the kernel's occupancy, larger values are clamped to it).  Sample calls,
+ * batches and served requests take the entry of their class (a batch or a
+ * served batch: the class of its total sample count for the leaf grid);
+ * the DCS_CUT_BIAS and DCS_LEAF_GRID environment variables override the
+ * table.  Geometry never changes a sample.  The table is per process, all
+ * classes start at (0, 0); dcs_workspace_size sizes for the current table.
+ * Errors: DCS_EINVAL for variant not 0/1, log2_n > 63, |cut_bias| > 16,
+ * leaf_wgs_per_cu > 64 or a NULL output pointer.
+ */
+int32_t dcs_tune_set(int32_t variant, uint32_t log2_n, int32_t cut_bias, uint32_t leaf_wgs_per_cu);
+int32_t dcs_tune_get(int32_t variant, uint32_t log2_n, int32_t* cut_bias,
+                     uint32_t* leaf_wgs_per_cu);
+int32_t dcs_tune_reset(void);
+
 /* Human-readable name of a status code (static storage). */
 const char* dcs_status_string(int32_t status);
 

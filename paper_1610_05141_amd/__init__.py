@@ -15,7 +15,8 @@ from dataclasses import dataclass
 __all__ = [
     "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
-    "profile_read", "debug_primitive", "EXPORTED_SYMBOLS", "LIB_PATH",
+    "profile_read", "debug_primitive", "tune_set", "tune_get", "tune_reset",
+    "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,6 +33,7 @@ EXPORTED_SYMBOLS = (
     "dcs_profile_read", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
+    "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset",
 )
 
 
@@ -112,12 +114,18 @@ def lib() -> ctypes.CDLL:
             "dcs_server_destroy": (i32, [vp]),
             "dcs_server_now": (dbl, []),
             "dcs_server_copy_out": (i32, [vp, u64, vp, vp]),
+            "dcs_tune_set": (i32, [i32, u32, i32, u32]),
+            "dcs_tune_get": (i32, [i32, u32, ctypes.POINTER(i32), ctypes.POINTER(u32)]),
+            "dcs_tune_reset": (i32, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        # launch geometry from the committed tuning table (never changes a sample)
+        from . import autotune
+        autotune.apply_table(L)
     return _lib
 
 
@@ -254,6 +262,22 @@ class Batch:
 
 def profile_enable(on: bool = True) -> None:
     _check(lib().dcs_profile_enable(1 if on else 0), "dcs_profile_enable")
+
+
+def tune_set(variant: int, log2_n: int, cut_bias: int, leaf_wgs_per_cu: int) -> None:
+    """Launch geometry of size class (variant, floor(log2 n)); never changes a sample."""
+    _check(lib().dcs_tune_set(variant, log2_n, cut_bias, leaf_wgs_per_cu), "dcs_tune_set")
+
+
+def tune_get(variant: int, log2_n: int):
+    """(cut_bias, leaf_wgs_per_cu) of a size class."""
+    cb, w = ctypes.c_int32(0), ctypes.c_uint32(0)
+    _check(lib().dcs_tune_get(variant, log2_n, ctypes.byref(cb), ctypes.byref(w)), "dcs_tune_get")
+    return int(cb.value), int(w.value)
+
+
+def tune_reset() -> None:
+    _check(lib().dcs_tune_reset(), "dcs_tune_reset")
 
 
 def profile_read(kind: int):

@@ -211,11 +211,29 @@ int32_t device_ctx(DeviceCtx** out) {
     c.leaf_occupancy = dcs::leaf_occupancy();
     c.bern_occupancy = dcs::bern_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
-    if (const char* e = getenv("DCS_CUT_BIAS")) c.cut_bias = atoi(e);
+
     c.init = true;
   }
   *out = &c;
   return DCS_OK;
+}
+
+// ---- tuning table ------------------------------------------------------------
+Tune g_tune[2][kTuneClasses];
+
+uint32_t size_class(uint64_t n) { return n ? 63u - static_cast<uint32_t>(__builtin_clzll(n)) : 0u; }
+
+Tune tune_for(uint32_t variant, uint64_t n) { return g_tune[variant ? 1 : 0][size_class(n)]; }
+
+int32_t cut_bias_for(uint32_t variant, uint64_t n) {
+  static const char* env = getenv("DCS_CUT_BIAS");
+  return env ? atoi(env) : tune_for(variant, n).cut_bias;
+}
+
+uint32_t leaf_wgs_for(const DeviceCtx* c, uint32_t variant, uint64_t n) {
+  const uint32_t occ = static_cast<uint32_t>(std::max(1, c->leaf_occupancy));
+  const uint32_t w = tune_for(variant, n).leaf_wgs_per_cu;
+  return w == 0 ? occ : std::min(w, occ);
 }
 
 // Library-owned workspace of at least `bytes` (grown on demand).
@@ -255,7 +273,7 @@ void timing_end(hipStream_t s, Timing* t) {
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors) {
+                          bool register_errors, uint32_t leaf_wgs_per_cu) {
   if (leaf_cap >= dcs::kMaxLeafJobs) return DCS_ENOMEM;
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
@@ -275,7 +293,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
                          ctl, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
-  uint64_t want = static_cast<uint64_t>(c->cus) * c->leaf_occupancy;
+  uint64_t want = static_cast<uint64_t>(c->cus) * std::max<uint32_t>(1, leaf_wgs_per_cu);
   if (c->leaf_grid > 0) want = static_cast<uint64_t>(c->leaf_grid);
   want = std::max<uint64_t>(1, std::min<uint64_t>(want, leaf_cap));
   Timing t4{}, t5{};
@@ -309,7 +327,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   DeviceCtx* c;
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
-  const Plan pl = make_plan(n, N, P.n0, variant, c->cut_bias);
+  const Plan pl = make_plan(n, N, P.n0, variant, cut_bias_for(variant, n));
   const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
   void* ws = workspace;
   if (ws == nullptr) {
@@ -331,7 +349,8 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   I.cut = pl.cut;
   I.top_cut = pl.top_cut;
   return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.top_threads, pl.leaf_cap,
-                           pl.stack_depth, out, static_cast<hipStream_t>(stream), true);
+                           pl.stack_depth, out, static_cast<hipStream_t>(stream), true,
+                           leaf_wgs_for(c, variant, n));
 }
 
 struct BernLayout {
@@ -451,7 +470,9 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
   if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
   if (variant == 0 || variant == 1) {
     if (variant == 0 && n > N) return DCS_EINVAL;
-    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant), 0);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant),
+                              cut_bias_for(static_cast<uint32_t>(variant), n));
     *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads).total;
     return DCS_OK;
   }
@@ -491,6 +512,7 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
                          uint32_t* bad_index) {
   if (batch == nullptr || (count > 0 && instances == nullptr) || count == 0) return DCS_EINVAL;
   *batch = nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
   auto* b = new dcs_batch();
   uint64_t tb = 0, tt = 0;
   for (uint32_t i = 0; i < count; ++i) {
@@ -504,7 +526,7 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
       delete b;
       return DCS_EINVAL;
     }
-    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant, 0);
+    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant, cut_bias_for(d.variant, d.n));
     Instance I{};
     I.n = d.n;
     I.N = d.N;
@@ -555,7 +577,8 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
   const uint32_t n_inst = static_cast<uint32_t>(b->host.size());
   if (!use_graph || g_profile) {
     return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
-                             b->leaf_cap, b->stack_depth, out_dev, s, true);
+                             b->leaf_cap, b->stack_depth, out_dev, s, true,
+                             leaf_wgs_for(c, 0, b->total_out));
   }
   if (s == nullptr) return DCS_EINVAL;  // capture needs a real stream
   if (b->exec == nullptr || b->graph_out != out_dev) {
@@ -569,7 +592,8 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DCS_EHIP;
     rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
-                           b->leaf_cap, b->stack_depth, out_dev, s, true);
+                           b->leaf_cap, b->stack_depth, out_dev, s, true,
+                           leaf_wgs_for(c, 0, b->total_out));
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != DCS_OK) return rc;
@@ -635,6 +659,33 @@ const char* dcs_status_string(int32_t st) {
     case DCS_ENOTSUP: return "not supported";
     default: return "unknown status";
   }
+}
+
+int32_t dcs_tune_set(int32_t variant, uint32_t log2_n, int32_t cut_bias, uint32_t leaf_wgs_per_cu) {
+  if ((variant != 0 && variant != 1) || log2_n >= kTuneClasses || cut_bias < -16 || cut_bias > 16 ||
+      leaf_wgs_per_cu > 64)
+    return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune[variant][log2_n] = Tune{cut_bias, leaf_wgs_per_cu};
+  return DCS_OK;
+}
+
+int32_t dcs_tune_get(int32_t variant, uint32_t log2_n, int32_t* cut_bias,
+                     uint32_t* leaf_wgs_per_cu) {
+  if ((variant != 0 && variant != 1) || log2_n >= kTuneClasses || cut_bias == nullptr ||
+      leaf_wgs_per_cu == nullptr)
+    return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *cut_bias = g_tune[variant][log2_n].cut_bias;
+  *leaf_wgs_per_cu = g_tune[variant][log2_n].leaf_wgs_per_cu;
+  return DCS_OK;
+}
+
+int32_t dcs_tune_reset(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& row : g_tune)
+    for (auto& t : row) t = Tune{};
+  return DCS_OK;
 }
 
 int32_t dcs_profile_enable(int32_t enable) {

@@ -47,12 +47,28 @@ struct DeviceCtx {
   int leaf_occupancy = 2;
   int bern_occupancy = 2;
   // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
-  // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut
+  // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut;
+  // when set they take precedence over the tuning table
   int64_t leaf_grid = 0;
-  int32_t cut_bias = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
 };
+
+// Tuned launch geometry of a size class (variant, floor(log2 n)), set through
+// dcs_tune_set; never changes a sample.
+struct Tune {
+  int32_t cut_bias = 0;          // added to the Algorithm P cut depth
+  uint32_t leaf_wgs_per_cu = 0;  // leaf work-groups per compute unit, 0 = occupancy
+};
+constexpr uint32_t kTuneClasses = 64;
+// Entry for an instance of n samples (caller holds lock()).
+Tune tune_for(uint32_t variant, uint64_t n);
+// Cut bias for an instance: the DCS_CUT_BIAS override, else the table's
+// (caller holds lock()).
+int32_t cut_bias_for(uint32_t variant, uint64_t n);
+// Leaf work-groups per compute unit for a launch whose largest class is
+// (variant, n): the table's, clamped to the kernel's occupancy.
+uint32_t leaf_wgs_for(const DeviceCtx* c, uint32_t variant, uint64_t n);
 
 // The library lock (guards the per-device contexts, the latched-error
 // registry and kernel timing).
@@ -61,10 +77,12 @@ std::mutex& lock();
 int32_t device_ctx(DeviceCtx** out);
 // Enqueue reset + tree + leaf on `s` for the instances in the workspace
 // (`single` != NULL: store that one instance first); caller holds lock().
+// Leaf work-groups: DCS_LEAF_GRID if set, else cus * leaf_wgs_per_cu (both
+// leaf kernels use it).
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors);
+                          bool register_errors, uint32_t leaf_wgs_per_cu);
 
 }  // namespace host
 }  // namespace dcs

@@ -247,9 +247,13 @@ constexpr uint8_t kNet16[63][2] = {
     {5, 13},  {5, 9},   {3, 11},  {7, 15},  {7, 11},  {3, 5},   {7, 9},   {11, 13},
     {1, 2},   {3, 4},   {5, 6},   {7, 8},   {9, 10},  {11, 12}, {13, 14}};
 
-__device__ __forceinline__ void sort16(uint32_t (&v)[16]) {
+// The first 19 comparators sort inputs 0..7: Batcher's network for 8.
+template <int W>
+__device__ __forceinline__ void sort_net(uint32_t (&v)[W]) {
+  static_assert(W == 8 || W == 16, "networks for 8 and 16 inputs");
+  constexpr int kComparators = W == 16 ? 63 : 19;
 #pragma unroll
-  for (int c = 0; c < 63; ++c) {
+  for (int c = 0; c < kComparators; ++c) {
     const uint32_t a = v[kNet16[c][0]], b = v[kNet16[c][1]];
     v[kNet16[c][0]] = min(a, b);
     v[kNet16[c][1]] = max(a, b);
@@ -267,32 +271,35 @@ __device__ __forceinline__ uint32_t wave_max_incl(uint32_t x) {
   return x;
 }
 
-// Sorts the 16-key windows keys[off + 16i .. off + 16i + 16) that start
-// below n (entries past n are 0xFFFFFFFF sentinels).  Returns nonzero in
-// every lane of a wave if one of its windows holds equal neighbours among
-// its first n entries.
-template <int B>
+// Sorts the W-key windows keys[off + Wi .. off + Wi + W) that start below n
+// (entries past n are 0xFFFFFFFF sentinels).  Returns nonzero in every lane
+// of a wave if one of its windows holds equal neighbours among its first n
+// entries.
+template <int B, int W>
 __device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint32_t off,
                                                 uint32_t tid) {
+  static_assert(W * B >= kKeys, "one window per thread");
   uint64_t dup = 0;
-  const uint32_t w0 = off + 16 * tid;  // 16 B <= kKeys: one window per thread
+  const uint32_t w0 = off + W * tid;
   if (w0 < n) {
     uint4* p = reinterpret_cast<uint4*>(keys + w0);
-    uint32_t v[16];
+    uint32_t v[W];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < W / 4; ++q) {
       const uint4 x = p[q];
       v[4 * q] = x.x;
       v[4 * q + 1] = x.y;
       v[4 * q + 2] = x.z;
       v[4 * q + 3] = x.w;
     }
-    sort16(v);
+    sort_net<W>(v);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    for (int q = 0; q < W / 4; ++q)
+      p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     const uint32_t lim = n - w0;  // entries of this window below n
 #pragma unroll
-    for (int i = 0; i < 15; ++i) dup |= __ballot(v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
+    for (int i = 0; i + 1 < W; ++i)
+      dup |= __ballot(v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
   }
   return dup;
 }
@@ -308,10 +315,11 @@ __device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint
 //      ones zero), which also finds the largest bucket c_max;
 //   3. scatter into sm.keys in bucket order;
 //   4. order inside the buckets.  Sorting any window of bucket-ordered keys
-//      only permutes keys within buckets, so sorting the 16-key windows at
-//      16i and then those at 16i + 8 sorts every bucket of at most 9 keys (it
-//      lies inside a window of one of the two passes), and equal keys, which
-//      share a bucket, meet as neighbours inside such a window.  Larger
+//      only permutes keys within buckets, so sorting the W-key windows at Wi
+//      and then those at Wi + W/2 sorts every bucket of at most W/2 + 1 keys
+//      (it lies inside a window of one of the two passes), and equal keys,
+//      which share a bucket, meet as neighbours inside such a window; W = 8
+//      when c_max <= 5, W = 16 when c_max <= 9.  Larger
 //      buckets (c_max > 9, rare) take c_max odd-even transposition rounds
 //      over the whole array -- a pair that spans two buckets never swaps, so
 //      each bucket is sorted after as many rounds as it has keys -- and a
@@ -329,7 +337,7 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   constexpr int kBlk = kKeys / (4 * B);
   constexpr int kPer = kBuckets / B;  // buckets per thread in the scan
   constexpr int kPairs = kKeys / (2 * B);
-  static_assert(kPer == 8 && kBuckets % 8 == 0, "scan runs are 8 counters + 1 pad word");
+  static_assert(kPer >= 1 && 8 % kPer == 0, "a scan run stays inside one padded group of 8");
   (void)nb;
   const uint32_t tid = lane_tid();
   const uint32_t wave_first = tid & ~63u;
@@ -366,9 +374,10 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
     }
   }
   __syncthreads();
-  // 2. scan: thread tid owns buckets [8 tid, 8 tid + 8) at words 9 tid ..
+  // 2. scan: thread tid owns buckets [kPer tid, kPer tid + kPer), contiguous
+  // words from bpad(kPer tid)
   {
-    uint32_t* run8 = cnt + 9 * tid;
+    uint32_t* run8 = cnt + bpad(kPer * tid);
     uint32_t c[kPer];
     uint32_t run = 0, big = 0;
 #pragma unroll
@@ -408,9 +417,16 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   if (shift == 0) return cmax >= 2 ? 1u : 0u;
   if (cmax <= 1) return 0u;
   if (cmax <= 9) {
-    uint64_t dup = window_pass<B>(keys, n, 0, tid);
-    __syncthreads();
-    dup |= window_pass<B>(keys, n, 8, tid);
+    uint64_t dup;
+    if (cmax <= 5) {
+      dup = window_pass<B, 8>(keys, n, 0, tid);
+      __syncthreads();
+      dup |= window_pass<B, 8>(keys, n, 4, tid);
+    } else {
+      dup = window_pass<B, 16>(keys, n, 0, tid);
+      __syncthreads();
+      dup |= window_pass<B, 16>(keys, n, 8, tid);
+    }
     if (dup && (tid & 63) == 0) sm.scr[kScrDups] = 1;
     __syncthreads();
     return sm.scr[kScrDups];

@@ -178,15 +178,18 @@ bool dcs_server::launch_batch() {
     pending.pop_front();
   }
   if (batch.empty()) return false;
-  // instance table
+  // instance table (planned under the library lock: it reads the tuning table)
+  std::lock_guard<std::mutex> lk(dcs::host::lock());
   std::vector<Instance> inst;
-  uint64_t threads = 0, top_threads = 0, leaf_cap = 0;
+  uint64_t threads = 0, top_threads = 0, leaf_cap = 0, total_n = 0;
   uint32_t stack_depth = 1;
   inst.reserve(batch.size());
   for (uint64_t tk : batch) {
     const Req& R = reqs[tk];
     const uint32_t n0 = R.r.n0 ? R.r.n0 : 4096u;
-    const Plan pl = dcs::host::make_plan(R.r.n, R.r.N, n0, R.r.variant, 0);
+    const Plan pl = dcs::host::make_plan(R.r.n, R.r.N, n0, R.r.variant,
+                                         dcs::host::cut_bias_for(R.r.variant, R.r.n));
+    total_n += R.r.n;
     Instance I{};
     I.n = R.r.n;
     I.N = R.r.N;
@@ -207,7 +210,6 @@ bool dcs_server::launch_batch() {
   }
   const uint32_t n_inst = static_cast<uint32_t>(inst.size());
   const TreeLayout L = dcs::host::tree_layout(n_inst, leaf_cap, threads, stack_depth, top_threads);
-  std::lock_guard<std::mutex> lk(dcs::host::lock());
   if (sl->ws_bytes < L.total) {
     if (sl->ws) {
       if (hipStreamSynchronize(sl->stream) != hipSuccess || hipFree(sl->ws) != hipSuccess) {
@@ -246,7 +248,8 @@ bool dcs_server::launch_batch() {
   }
   int32_t rc = dcs::host::run_tree_pipeline(c, sl->ws, L, nullptr, n_inst, threads, top_threads,
                                             leaf_cap, stack_depth,
-                                            reinterpret_cast<uint64_t*>(arena), sl->stream, false);
+                                            reinterpret_cast<uint64_t*>(arena), sl->stream, false,
+                                            dcs::host::leaf_wgs_for(c, 0, total_n));
   if (rc == DCS_OK &&
       (hipMemcpyAsync(sl->err, &reinterpret_cast<Control*>(base + L.ctl)->error,
                       sizeof(unsigned int), hipMemcpyDeviceToHost, sl->stream) != hipSuccess ||

@@ -78,3 +78,32 @@ def test_config4_batch_4096(ref):
         out2.zero_()
         torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_with_recorded_leaf_sizes(ref):
+    """Instances carry their own leaf size (as the autotuner records them per
+    class): mixed n0 in one batch, each instance equal to the oracle run with
+    that n0."""
+    import torch
+    m = dcs()
+    from paper_1610_05141_amd import autotune
+    announce("batch with per-instance leaf sizes")
+    insts = batched_instances(160, n_lo_log2=4, n_hi_log2=17, key=4242)
+    choices = autotune.N0_CHOICES
+    specs, off = [], 0
+    for i, x in enumerate(insts):
+        n0 = autotune.n0_for(x.n, x.N) if i % 2 else choices[i % len(choices)]
+        specs.append(m.InstanceSpec(n=x.n, N=x.N, seed=x.seed, out_offset=off, n0=n0))
+        off += x.n
+    b = m.Batch(specs)
+    out = torch.full((off,), -1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.run(out, use_graph=True, stream=stream)
+    m.synchronize(stream)
+    got = to_np_u64(out)
+    for s, x in zip(specs, insts):
+        want = ref.sample(x.n, x.N, x.seed, n0=s.n0)
+        g = got[s.out_offset:s.out_offset + x.n]
+        assert np.array_equal(g, want), f"{x} n0={s.n0}: {first_mismatch(g, want)}"
+    b.close()

@@ -53,3 +53,29 @@ def test_launch_geometry_invariance(ref):
                 {"DCS_LEAF_GRID": "5000"}, {"DCS_CUT_BIAS": "-4"},
                 {"DCS_CUT_BIAS": "3"}, {"DCS_LEAF_GRID": "13", "DCS_CUT_BIAS": "-20"}]:
         assert _run(env) == want, env
+
+
+def test_tuning_table_geometry_invariance(ref):
+    """Entries of the library's tuning table (what the autotuner sets) change
+    the launch geometry of a size class, never its sample."""
+    import torch
+    from tests.gpu_util import dcs, to_np_u64
+    m = dcs()
+    cases = [(0, 1 << 20, 1 << 32, 1), (0, 300000, 700000, 3), (1, 200000, 3 * 10**6 + 1, 5)]
+    saved = {}
+    try:
+        for variant, n, N, seed in cases:
+            k = n.bit_length() - 1
+            saved[(variant, k)] = m.tune_get(variant, k)
+            want = ref.sample(n, N, seed) if variant == 0 else ref.replacement(n, N, seed)
+            for cb, w in [(-2, 1), (2, 3), (0, 2), (-16, 1), (5, 64)]:
+                print(f"[gpu-step] tuned geometry variant={variant} n={n} cut_bias={cb} wgs={w}",
+                      flush=True)
+                m.tune_set(variant, k, cb, w)
+                f = m.sample if variant == 0 else m.sample_replacement
+                got = to_np_u64(f(n, N, seed))
+                m.synchronize()
+                assert np.array_equal(got, want), (variant, n, cb, w)
+    finally:
+        for (variant, k), (cb, w) in saved.items():
+            m.tune_set(variant, k, cb, w)
