@@ -247,13 +247,16 @@ constexpr uint8_t kNet16[63][2] = {
     {5, 13},  {5, 9},   {3, 11},  {7, 15},  {7, 11},  {3, 5},   {7, 9},   {11, 13},
     {1, 2},   {3, 4},   {5, 6},   {7, 8},   {9, 10},  {11, 12}, {13, 14}};
 
-// The first 19 comparators sort inputs 0..7: Batcher's network for 8.
-template <int W>
+// The first 19 comparators sort inputs 0..7: Batcher's network for 8.  The
+// last 9 of those (and the last 25 of the 16-input network) are the final
+// merge stage, which alone sorts an input whose two halves are sorted.
+template <int W, bool kMergeOnly>
 __device__ __forceinline__ void sort_net(uint32_t (&v)[W]) {
   static_assert(W == 8 || W == 16, "networks for 8 and 16 inputs");
-  constexpr int kComparators = W == 16 ? 63 : 19;
+  constexpr int kEnd = W == 16 ? 63 : 19;
+  constexpr int kBegin = kMergeOnly ? (W == 16 ? 38 : 10) : 0;
 #pragma unroll
-  for (int c = 0; c < kComparators; ++c) {
+  for (int c = kBegin; c < kEnd; ++c) {
     const uint32_t a = v[kNet16[c][0]], b = v[kNet16[c][1]];
     v[kNet16[c][0]] = min(a, b);
     v[kNet16[c][1]] = max(a, b);
@@ -272,10 +275,11 @@ __device__ __forceinline__ uint32_t wave_max_incl(uint32_t x) {
 }
 
 // Sorts the W-key windows keys[off + Wi .. off + Wi + W) that start below n
-// (entries past n are 0xFFFFFFFF sentinels).  Returns nonzero in every lane
-// of a wave if one of its windows holds equal neighbours among its first n
-// entries.
-template <int B, int W>
+// (entries past n are 0xFFFFFFFF sentinels); kMergeOnly: each window's halves
+// are already sorted.  Returns, in each lane, the ballot over the lanes that
+// took the same branch: nonzero in some lane of the wave iff one of its
+// windows holds equal neighbours among its first n entries.
+template <int B, int W, bool kMergeOnly>
 __device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint32_t off,
                                                 uint32_t tid) {
   static_assert(W * B >= kKeys, "one window per thread");
@@ -292,14 +296,19 @@ __device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint
       v[4 * q + 2] = x.z;
       v[4 * q + 3] = x.w;
     }
-    sort_net<W>(v);
+    sort_net<W, kMergeOnly>(v);
 #pragma unroll
     for (int q = 0; q < W / 4; ++q)
       p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    const uint32_t lim = n - w0;  // entries of this window below n
+    if (w0 + W <= n) {  // the whole window lies below n
 #pragma unroll
-    for (int i = 0; i + 1 < W; ++i)
-      dup |= __ballot(v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
+      for (int i = 0; i + 1 < W; ++i) dup |= __ballot(v[i] == v[i + 1]);
+    } else {
+      const uint32_t lim = n - w0;  // entries of this window below n
+#pragma unroll
+      for (int i = 0; i + 1 < W; ++i)
+        dup |= __ballot(v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
+    }
   }
   return dup;
 }
@@ -330,8 +339,20 @@ __device__ __forceinline__ uint64_t window_pass(uint32_t* keys, uint32_t n, uint
 // counter whose scanned start is a spare slot, so the passes carry no
 // per-key branches.  Each key keeps its counter index | slot << 16 in one
 // register between the passes.
+// kLazyZero: the counters are zero on entry and are zeroed again once read
+// (during the first window pass), and the sentinels and the duplicate flag
+// are written after the counting barrier, so that a caller may start the next
+// sort without a barrier after this sort's result has been read; otherwise
+// everything is cleared on entry.
 // ---------------------------------------------------------------------------
 template <int B>
+__device__ __forceinline__ void zero_counters(uint32_t* cnt, uint32_t tid) {
+  for (uint32_t w = tid; w < kSpareCount / 4; w += B)
+    reinterpret_cast<uint4*>(cnt)[w] = make_uint4(0, 0, 0, 0);
+  if (tid == 0) cnt[kSpareCount] = 0;
+}
+
+template <int B, bool kLazyZero = false>
 __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n, uint32_t shift,
                                    uint32_t nb, LeafSmem& sm) {
   constexpr int kBlk = kKeys / (4 * B);
@@ -344,14 +365,12 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   uint32_t* cnt = sm.buck;
   uint32_t* keys = sm.keys;
   // 1. zero the counters, sentinels after the keys, count
-  for (uint32_t w = tid; w < kSpareCount / 4; w += B)
-    reinterpret_cast<uint4*>(cnt)[w] = make_uint4(0, 0, 0, 0);
-  if (tid < 24) keys[n + tid] = 0xFFFFFFFFu;
-  if (tid == 0) {
-    sm.scr[kScrDups] = 0;
-    cnt[kSpareCount] = 0;
+  if (!kLazyZero) {
+    zero_counters<B>(cnt, tid);
+    if (tid < 24) keys[n + tid] = 0xFFFFFFFFu;
+    if (tid == 0) sm.scr[kScrDups] = 0;
+    __syncthreads();
   }
-  __syncthreads();
   uint32_t as[4 * kBlk];
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
@@ -376,6 +395,10 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   __syncthreads();
   // 2. scan: thread tid owns buckets [kPer tid, kPer tid + kPer), contiguous
   // words from bpad(kPer tid)
+  if (kLazyZero) {
+    if (tid < 24) keys[n + tid] = 0xFFFFFFFFu;
+    if (tid == 0) sm.scr[kScrDups] = 0;
+  }
   {
     uint32_t* run8 = cnt + bpad(kPer * tid);
     uint32_t c[kPer];
@@ -414,20 +437,28 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   }
   __syncthreads();
   // 4. order inside buckets
-  if (shift == 0) return cmax >= 2 ? 1u : 0u;
-  if (cmax <= 1) return 0u;
+  if (shift == 0 || cmax <= 1) {
+    if (kLazyZero) {
+      zero_counters<B>(cnt, tid);
+      __syncthreads();
+    }
+    return (shift == 0 && cmax >= 2) ? 1u : 0u;
+  }
+  if (kLazyZero) zero_counters<B>(cnt, tid);  // read for the last time in the scatter
   if (cmax <= 9) {
     uint64_t dup;
+    // the second pass's windows are two sorted halves of first-pass windows
     if (cmax <= 5) {
-      dup = window_pass<B, 8>(keys, n, 0, tid);
+      dup = window_pass<B, 8, false>(keys, n, 0, tid);
       __syncthreads();
-      dup |= window_pass<B, 8>(keys, n, 4, tid);
+      dup |= window_pass<B, 8, true>(keys, n, 4, tid);
     } else {
-      dup = window_pass<B, 16>(keys, n, 0, tid);
+      dup = window_pass<B, 16, false>(keys, n, 0, tid);
       __syncthreads();
-      dup |= window_pass<B, 16>(keys, n, 8, tid);
+      dup |= window_pass<B, 16, true>(keys, n, 8, tid);
     }
-    if (dup && (tid & 63) == 0) sm.scr[kScrDups] = 1;
+    // lanes of a wave may hold ballots of different branches: any of them sets it
+    if (dup) sm.scr[kScrDups] = 1;
     __syncthreads();
     return sm.scr[kScrDups];
   }
@@ -556,7 +587,7 @@ __device__ __forceinline__ void write_sorted_pairs(uint64_t* out, uint64_t base,
 // ---------------------------------------------------------------------------
 // Rounds after the first: keys[0..have) hold distinct values; draw the next
 // (nv - have) non-void values from word t on, sort, repeat while values repeat.
-template <int B>
+template <int B, bool kLazyZero = false>
 __device__ void sparse_rounds(const Stream& st, uint64_t t, uint32_t have, uint32_t nv,
                               const RangeInfo& ri, uint32_t shift, uint32_t nb, LeafSmem& sm) {
   uint32_t* keys = sm.keys;
@@ -567,7 +598,7 @@ __device__ void sparse_rounds(const Stream& st, uint64_t t, uint32_t have, uint3
                        [&](uint32_t p, uint32_t v) { keys[base + p] = v; });
     load_registers<B>(key, keys, nv);
     __syncthreads();
-    if (sort_registers<B>(key, nv, shift, nb, sm) == 0) return;
+    if (sort_registers<B, kLazyZero>(key, nv, shift, nb, sm) == 0) return;
     have = compact_distinct<B>(keys, sm.tmp, sm.scr, nv);
   }
 }
@@ -609,9 +640,9 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
       key[4 * k + 3] = w.w >> pshift;
     }
   }
-  if (sort_registers<B>(key, nv, shift, nb, sm) != 0) {
+  if (sort_registers<B, true>(key, nv, shift, nb, sm) != 0) {
     const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
-    sparse_rounds<B>(st, nv, have, nv, range_info(L.Nv), shift, nb, sm);
+    sparse_rounds<B, true>(st, nv, have, nv, range_info(L.Nv), shift, nb, sm);
   }
   write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
@@ -766,7 +797,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
   sm.mask = sm.buck + kKeys;
   uint32_t* cache = smem + kRegionA + kRegionB;
   sm.scr = cache + kCacheWords;
-  const unsigned long long counts = ctl->leaf_counts;
+  const uint64_t counts = uniform64(ctl->leaf_counts);
   const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
   if (front + back > leaf_cap) {
     // the lists overlap (or one overflowed): the tree kernel flagged or
@@ -776,6 +807,11 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
   }
   const uint64_t n_leaves = kPow2 ? front : back;
   const uint64_t G = gridDim.x;
+  if (kPow2) {
+    // the power-of-two leaf sorts leave the bucket counters zeroed behind them
+    zero_counters<B>(sm.buck, threadIdx.x);
+    __syncthreads();
+  }
   for (uint64_t j = 0;; ++j) {
     const uint64_t i = blockIdx.x + j * G;
     if (i >= n_leaves) break;
@@ -816,6 +852,10 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
       L.flags = __builtin_amdgcn_readfirstlane(L.flags);
     }
     if constexpr (kPow2) {
+      // No barrier after the leaf: the next leaf's first LDS writes (counting
+      // atomics into zeroed counters) do not touch what this leaf's output
+      // pass still reads, and its sentinels and flag wait for the counting
+      // barrier, which every thread reaches only after its output pass.
       leaf_sparse_pow2<B>(L, out, sm);
     } else {
       switch (L.flags & 3u) {
@@ -824,8 +864,8 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
         case kKindWr: leaf_wr<B>(L, out, sm); break;
         default: leaf_fill<B>(L, out); break;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

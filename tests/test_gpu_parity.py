@@ -32,6 +32,10 @@ WOR_CASES = [
     (200, 2**52, 15, 4096, 16),               # largest universe
     (3, 2**52, 16, 2, 16),                    # n0 = 2, depth 50
     (20000, 640000, 17, 4096, 16),            # density 1/32: sparse, duplicates common
+    # ~17 repeated draws per leaf over ~1500 leaves: repeats inside the last
+    # sorting window of a leaf, power-of-two and other leaf ranges
+    (1 << 22, 1 << 28, 21, 4096, 16),
+    (1 << 22, 3 * 2**26 + 5, 22, 4096, 16),
 ]
 
 
