@@ -669,7 +669,7 @@ __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
 // ---------------------------------------------------------------------------
 template <int B>
 __device__ void leaf_dense(const Leaf& L, uint64_t* out, LeafSmem& sm) {
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = lane_tid();
   const uint32_t nv = L.nv;
   const uint32_t Nv = static_cast<uint32_t>(L.Nv);  // < 64 * 4096 here
   const uint32_t n0 = L.flags >> 8;
@@ -687,70 +687,68 @@ __device__ void leaf_dense(const Leaf& L, uint64_t* out, LeafSmem& sm) {
     if (full) {
       hits = Nv;
     } else {
+      // Hit k sits at 0-based position q_k - 1, q_k = sum_{i<=k} (skip_i + 1);
+      // each round takes 4 draws per thread in stream order and one scan.
+      // A skip is below 2^24 and Nv + round sums stay far below 2^32.
       const Stream st = make_stream(L.seed, L.id, kBern, attempt);
-      int64_t last = -1;  // position of the last word of the previous round
+      uint32_t last = 0;  // q of the previous round's last draw
       uint32_t count = 0;
       for (uint32_t blk0 = 0;; blk0 += B) {
         const uint4 w = philox_block(st, blk0 + tid);
-        int32_t inc[4];
+        uint32_t inc[4];
         uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          inc[j] = geom_skip32(pick(w, j), cg) + 1;
-          sum += static_cast<uint32_t>(inc[j]);
+          inc[j] = static_cast<uint32_t>(geom_skip32(pick(w, j), cg)) + 1u;
+          sum += inc[j];
         }
         uint32_t total;
-        const uint32_t before = block_scan_excl<B, uint32_t>(sum, sm.scr, &total);
-        int64_t p = last + static_cast<int64_t>(before);
-        uint32_t in = 0;
+        const uint32_t q0 = last + block_scan_excl<B, uint32_t>(sum, sm.scr, &total);
+        uint32_t q = q0, in = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          p += inc[j];
-          if (p < static_cast<int64_t>(Nv)) {
+          q += inc[j];
+          if (q <= Nv) {
             ++in;
             const uint32_t idx = count + 4u * tid + j;  // stream index = hit index
-            if (idx <= cap) pos[idx] = static_cast<uint32_t>(p);
+            if (idx <= cap) pos[idx] = q - 1;
           }
         }
-        // positions below Nv form a prefix of the round: count the threads
-        // with all four in, plus the one partial thread
-        const uint32_t full_threads = static_cast<uint32_t>(__syncthreads_count(in == 4 ? 1 : 0));
-        const uint32_t partial = static_cast<uint32_t>(__syncthreads_count(in > 0 && in < 4 ? 1 : 0));
-        uint32_t round_in = 4u * full_threads;
-        if (partial) {
-          if (in > 0 && in < 4) sm.scr[kScrNext] = in;
-          __syncthreads();
-          round_in += sm.scr[kScrNext];
-          __syncthreads();
+        if (last + total <= Nv) {  // every draw of the round is a hit
+          count += 4u * B;
+          last += total;
+          if (count > cap) break;
+          continue;
         }
-        count += round_in;
-        last += static_cast<int64_t>(total);
-        if (round_in < 4u * B || count > cap) break;
+        // hits are a prefix of the round: the one thread that starts in range
+        // and holds the first miss reports how many
+        if (in < 4 && q0 <= Nv) sm.scr[kScrNext] = 4u * tid + in;
+        __syncthreads();
+        count += sm.scr[kScrNext];
+        __syncthreads();
+        break;
       }
       hits = count;
       if (hits < nv || hits > cap) continue;
     }
     // Repair: remove the first (hits - nv) distinct values of the REPAIR
-    // stream mapped into [0, hits).
+    // stream mapped into [0, hits); a value counts when its bit was clear.
     const uint32_t r = hits - nv;
     const uint32_t mwords = (hits + 31) / 32;
     for (uint32_t i = tid; i < mwords; i += B) sm.mask[i] = 0;
+    if (tid == 0) sm.scr[kScrDups] = 0;
     __syncthreads();
     if (r > 0) {
       const Stream sr = make_stream(L.seed, L.id, kRepair, attempt);
       const RangeInfo ri = range_info(hits);
-      uint32_t have = 0;
       uint64_t t = 0;
-      for (;;) {
+      for (uint32_t have = 0; have < r;) {
         t = take_values<B>(sr, t, r - have, ri, sm.scr, [&](uint32_t, uint32_t v) {
-          atomicOr(&sm.mask[v >> 5], 1u << (v & 31));
+          const uint32_t bit = 1u << (v & 31);
+          if (!(atomicOr(&sm.mask[v >> 5], bit) & bit)) atomicAdd(&sm.scr[kScrDups], 1u);
         });
-        uint32_t c = 0;
-        for (uint32_t i = tid; i < mwords; i += B) c += __popc(sm.mask[i]);
-        uint32_t total;
-        block_scan_excl<B, uint32_t>(c, sm.scr, &total);
-        have = total;
-        if (have == r) break;
+        have = sm.scr[kScrDups];  // take_values ends with a barrier
+        __syncthreads();
       }
     }
     // Compact the kept hits (ascending position) into kept[0..nv).
@@ -768,7 +766,7 @@ __device__ void leaf_dense(const Leaf& L, uint64_t* out, LeafSmem& sm) {
       if (i < hits && !((sm.mask[i >> 5] >> (i & 31)) & 1u)) sm.kept[o++] = full ? i : pos[i];
     }
     __syncthreads();
-    write_sorted<B>(out + L.off, L.lo, sm.kept, nv);
+    write_sorted_pairs<B>(out + L.off, L.lo, sm.kept, nv);
     break;
   }
 }
