@@ -172,7 +172,7 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
             out = torch.empty(n, dtype=torch.int64, device="cuda")
             f = dcs.sample if kind == "wor" else dcs.sample_replacement
             run = lambda: f(n, N, seed, out=out, stream=stream)
-            kernels = {"k_leaf_pow2": 4, "k_leaf_mixed": 5}
+            kernels = {"k_leaf_pow2": 4, "k_leaf_mixed": 5, "k_leaf_dense": 6}
         run()
         dcs.synchronize(stream)
         dcs.profile_enable(True)
@@ -304,7 +304,8 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     stage_ms, stage_n = dcs.profile_read(2)
     leaf_ms, leaf_n = dcs.profile_read(4)     # the power-of-two sparse leaf kernel
-    mixed_ms, mixed_n = dcs.profile_read(5)   # leaf kernel of the other leaf kinds
+    mixed_ms, mixed_n = dcs.profile_read(5)   # work-group leaf kernel of the other kinds
+    dense_ms, dense_n = dcs.profile_read(6)   # one-wave dense leaf kernel
     tree_ms, tree_n = dcs.profile_read(1)
     reset_ms, reset_n = dcs.profile_read(0)
     dcs.profile_enable(False)
@@ -350,6 +351,7 @@ def main() -> int:
                                 "tree": tree_ms / max(tree_n, 1),
                                 "k_leaf_pow2": leaf_avg_ms,
                                 "k_leaf_mixed": mixed_ms / max(mixed_n, 1),
+                                "k_leaf_dense": dense_ms / max(dense_n, 1),
                                 "leaf_stage": stage_ms / max(stage_n, 1)},
         "whole_step_write_GBs": BYTES_PER_SAMPLE * N_SAMPLE / (ms_per_step * 1e-3) / 1e9,
         "invariants_ok": props_ok,

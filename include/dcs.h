@@ -242,9 +242,11 @@ const char* dcs_status_string(int32_t status);
  * launched on.  enable != 0 starts recording (and clears the totals).
  * dcs_profile_read: after the stream is synchronized, accumulated
  * milliseconds and launch count for kernel `kind`
- * (0 = reset, 1 = tree split, 2 = leaf stage: both leaf kernels,
+ * (0 = reset, 1 = tree split, 2 = leaf stage: all three leaf kernels,
  * 3 = Bernoulli chunk, 4 = leaf kernel of the sparse power-of-two jobs,
- * 5 = leaf kernel of all other jobs); DCS_EINVAL for another kind. */
+ * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
+ * kernel of the dense jobs with ranges up to 2^16); DCS_EINVAL for another
+ * kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 

@@ -282,9 +282,10 @@ def tune_reset() -> None:
 
 def profile_read(kind: int):
     """(total milliseconds, launches) of kernel kind 0 reset, 1 tree, 2 leaf
-    stage (both leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse
-    power-of-two jobs, 5 leaf kernel of the other jobs, accumulated since
-    profile_enable (read after synchronize)."""
+    stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse
+    power-of-two jobs, 5 work-group leaf kernel of the other jobs, 6
+    one-wave dense leaf kernel, accumulated since profile_enable (read after
+    synchronize)."""
     ms = ctypes.c_double(0)
     n = ctypes.c_uint64(0)
     _check(lib().dcs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dcs_profile_read")

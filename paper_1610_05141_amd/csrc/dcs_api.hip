@@ -191,9 +191,10 @@ std::vector<DeviceCtx> g_dev;
 std::set<void*> g_ctl_used;  // control blocks to check at synchronize
 bool g_profile = false;
 std::vector<Timing> g_timings;
-// kinds: 0 reset, 1 tree, 2 leaf stage (both leaf kernels), 3 Bernoulli,
-// 4 leaf kernel of the power-of-two sparse list, 5 leaf kernel of the rest
-constexpr int kProfKinds = 6;
+// kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
+// 4 leaf kernel of the power-of-two sparse list, 5 work-group leaf kernel of
+// the rest, 6 one-wave dense leaf kernel
+constexpr int kProfKinds = 7;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 
@@ -210,6 +211,7 @@ int32_t device_ctx(DeviceCtx** out) {
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
     c.bern_occupancy = dcs::bern_occupancy();
+    c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
 
     c.init = true;
@@ -305,6 +307,15 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
     timing_begin(5, s, &t5);
     e = dcs::launch_leaf(false, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
     timing_end(s, &t5);
+  }
+  Timing t6{};
+  if (e == hipSuccess) {
+    uint64_t waves = static_cast<uint64_t>(c->cus) * std::max(1, c->dense_occupancy);
+    if (c->leaf_grid > 0) waves = static_cast<uint64_t>(c->leaf_grid) * (dcs::kLeafBlock / 64);
+    waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, leaf_cap));
+    timing_begin(6, s, &t6);
+    e = dcs::launch_leaf_dense(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(waves), s);
+    timing_end(s, &t6);
   }
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;

@@ -771,6 +771,177 @@ __device__ void leaf_dense(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dense leaf, one wave per leaf (same sample as leaf_dense).
+// ---------------------------------------------------------------------------
+// Leaves whose range fits 16-bit positions are taken by k_leaf_dense, one
+// wave each with no barrier; the work-group leaf loop skips them.  With the
+// default dense ratio (16) and n0 <= 4096 that is every dense leaf.
+constexpr uint32_t kWaveMaxRange = 1u << 16;
+constexpr uint32_t kWaveChunk = 256;                             // draws per chunk
+constexpr uint32_t kWaveListChunks = 17;                         // chunks kept in LDS
+constexpr uint32_t kWaveList = kWaveChunk * kWaveListChunks;     // 4352 positions
+constexpr uint32_t kWaveMaskWords = (kDenseCap + 1 + 31) / 32 + 1;
+constexpr uint32_t kWaveBases = kDenseCap / kWaveChunk + 2;
+
+__device__ __forceinline__ bool dense_by_wave(const Leaf& L) {
+  return (L.flags & 3u) == kKindDense && L.Nv <= kWaveMaxRange;
+}
+
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+// Chunk c of the skip stream: lane l holds draws 256c + 4l + j (j < 4).  On
+// return q[j] is the 1-based position reached after draw j (the hit, if
+// q[j] <= Nv, sits at q[j] - 1) and the result is the chunk's total advance.
+__device__ __forceinline__ uint32_t skip_chunk(const Stream& st, uint32_t c, uint32_t lane,
+                                               float cg, uint32_t q_base, uint32_t q[4]) {
+  const uint4 w = philox_block(st, c * (kWaveChunk / 4) + lane);
+  uint32_t inc[4];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    inc[j] = static_cast<uint32_t>(geom_skip32(pick(w, j), cg)) + 1u;
+    sum += inc[j];
+  }
+  const uint32_t incl = wave_scan_incl(sum);
+  uint32_t x = q_base + incl - sum;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x += inc[j];
+    q[j] = x;
+  }
+  return __builtin_amdgcn_readlane(incl, 63);
+}
+
+// One wave samples one dense leaf (Algorithm B, Sec. 2, with geometric skips,
+// Sec. 4.7): hit positions as 16-bit values (chunks beyond kWaveListChunks
+// are recomputed from their start position when they are written out), the
+// repair's removed hit indices as a bit mask, and the kept hits written with
+// consecutive lanes on consecutive outputs.
+__device__ void leaf_dense_wave(const Leaf& L, uint64_t* out, uint16_t* list, uint32_t* mask,
+                                uint32_t* bases) {
+  const uint32_t lane = lane_tid();
+  const uint32_t nv = L.nv;
+  const uint32_t Nv = static_cast<uint32_t>(L.Nv);
+  const uint32_t n0 = L.flags >> 8;
+  const uint32_t rho_num = nv + 3u * static_cast<uint32_t>(isqrt64(nv)) + 8u;
+  const bool full = rho_num >= Nv;
+  float cg = 0.0f;
+  if (!full) {
+    const float rho = static_cast<float>(rho_num) / static_cast<float>(Nv);
+    cg = static_cast<float>(1.0 / log64(1.0 - static_cast<double>(rho)));
+  }
+  const uint32_t cap = 2u * n0 + 64u;
+  for (uint32_t attempt = 0;; ++attempt) {
+    const Stream st = make_stream(L.seed, L.id, kBern, attempt);
+    uint32_t cnt = 0;  // n'
+    if (full) {
+      cnt = Nv;
+    } else {
+      uint32_t q_base = 0;
+      for (uint32_t c = 0;; ++c) {
+        uint32_t q[4];
+        if (lane == 0) bases[c] = q_base;
+        const uint32_t adv = skip_chunk(st, c, lane, cg, q_base, q);
+        uint32_t in = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in += q[j] <= Nv ? 1u : 0u;
+        if (c < kWaveListChunks) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (q[j] <= Nv) list[c * kWaveChunk + 4u * lane + j] = static_cast<uint16_t>(q[j] - 1u);
+        }
+        // hits are a prefix of the chunk: whole lanes, then one partial lane
+        const unsigned long long whole = __ballot(in == 4u);
+        const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+        const uint32_t got =
+            nw == 64u ? kWaveChunk : 4u * nw + __builtin_amdgcn_readlane(in, nw);
+        cnt += got;
+        q_base += adv;
+        if (got < kWaveChunk || cnt > cap) break;
+      }
+      if (cnt < nv || cnt > cap) continue;
+    }
+    // Repair: remove the first (cnt - nv) distinct values of the REPAIR
+    // stream mapped into [0, cnt).  Words are taken 64 at a time in stream
+    // order (lane m holds word 64 j + m of a 256-word Philox round), so the
+    // r-th new value is found with a ballot.
+    const uint32_t r = cnt - nv;
+    const uint32_t mwords = (cnt + 31u) / 32u;
+    for (uint32_t i = lane; i < mwords; i += 64u) mask[i] = 0u;
+    if (r > 0) {
+      const Stream sr = make_stream(L.seed, L.id, kRepair, attempt);
+      const uint32_t thr = range_threshold(cnt);
+      uint32_t have = 0;
+      for (uint32_t it = 0; have < r; ++it) {
+        const uint4 w4 = philox_block(sr, it * 64u + lane);
+        for (uint32_t j = 0; j < 4u && have < r; ++j) {
+          const int src = static_cast<int>(16u * j + (lane >> 2));
+          const uint32_t x0 = __shfl(w4.x, src), x1 = __shfl(w4.y, src);
+          const uint32_t x2 = __shfl(w4.z, src), x3 = __shfl(w4.w, src);
+          const uint32_t cmp = lane & 3u;
+          const uint32_t word = cmp == 0 ? x0 : (cmp == 1 ? x1 : (cmp == 2 ? x2 : x3));
+          uint32_t v;
+          const bool ok = range_map(word, cnt, thr, &v);
+          const uint32_t bit = 1u << (v & 31u);
+          uint32_t* mw = mask + (v >> 5);
+          const bool fresh = ok && !(*mw & bit);
+          const uint32_t old = fresh ? atomicOr(mw, bit) : 0u;
+          // equal fresh values in one step: the lowest lane is the first
+          unsigned long long raced = __ballot(fresh && (old & bit));
+          bool later = false;
+          while (raced) {
+            const uint32_t s = static_cast<uint32_t>(__ffsll(static_cast<long long>(raced)) - 1);
+            const uint32_t vs = __builtin_amdgcn_readlane(v, s);
+            const unsigned long long same = __ballot(fresh && v == vs);
+            const uint32_t first = static_cast<uint32_t>(__ffsll(static_cast<long long>(same)) - 1);
+            later = later || (fresh && v == vs && lane != first);
+            raced &= ~same;
+          }
+          const bool firsts = fresh && !later;
+          const unsigned long long F = __ballot(firsts);
+          const uint32_t need = r - have;
+          // values past the r-th are not removed: take their bits back
+          if (firsts && lane_rank(F) >= need) atomicAnd(mw, ~bit);
+          const uint32_t nf = static_cast<uint32_t>(__popcll(F));
+          have += nf < need ? nf : need;
+        }
+      }
+    }
+    // Kept hits in order, consecutive lanes on consecutive outputs (exactly
+    // nv of them; the bound only keeps the stores inside the leaf's part).
+    uint64_t* const o0 = out + L.off;
+    uint32_t done = 0;
+    const uint64_t b1 = L.lo + 1;
+    constexpr uint32_t kSpare = (kWaveListChunks - 1) * kWaveChunk;  // recomputed chunks
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64u) {
+      const uint32_t k = k0 + lane;
+      uint32_t pos = k;
+      if (!full) {
+        const uint32_t c = k0 / kWaveChunk;
+        if (c >= kWaveListChunks && (k0 % kWaveChunk) == 0) {
+          uint32_t q[4];
+          skip_chunk(st, c, lane, cg, bases[c], q);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (q[j] <= Nv) list[kSpare + 4u * lane + j] = static_cast<uint16_t>(q[j] - 1u);
+        }
+        const uint32_t slot = c < kWaveListChunks ? k : kSpare + (k - c * kWaveChunk);
+        if (k < cnt) pos = list[slot];
+      }
+      const bool kept = k < cnt && !((mask[k >> 5] >> (k & 31u)) & 1u);
+      const unsigned long long K = __ballot(kept);
+      const uint32_t at = done + lane_rank(K);
+      if (kept && at < nv) store_out(o0 + at, b1 + pos);
+      done += static_cast<uint32_t>(__popcll(K));
+    }
+    break;
+  }
+}
+
 // Constant leaf of a with-replacement tree: N_v = 1, every draw is lo+1.
 template <int B>
 __device__ void leaf_fill(const Leaf& L, uint64_t* out) {
@@ -815,7 +986,10 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
     if (i >= n_leaves) break;
     const uint32_t slot = static_cast<uint32_t>(j % kCacheLeaves);
     if (slot == 0) {
-      // read the next kCacheLeaves job records of this work-group into LDS
+      // read the next kCacheLeaves job records of this work-group into LDS;
+      // skipped jobs end without a barrier, so wait until every thread has
+      // read the previous record
+      if constexpr (!kPow2) __syncthreads();
       const uint32_t tid = threadIdx.x;
       if (tid < kCacheLeaves * 3) {
         const uint32_t which = tid / 3, part = tid % 3;
@@ -856,6 +1030,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
       // barrier, which every thread reaches only after its output pass.
       leaf_sparse_pow2<B>(L, out, sm);
     } else {
+      if (dense_by_wave(L)) continue;  // k_leaf_dense's
       switch (L.flags & 3u) {
         case kKindSparse: leaf_sparse<B>(L, out, sm); break;
         case kKindDense: leaf_dense<B>(L, out, sm); break;
@@ -877,6 +1052,31 @@ template <int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_mixed(
     const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl) {
   leaf_loop<B, false>(leaves, leaf_cap, out, ctl);
+}
+
+// Dense leaves of the back list, one wave (and work-group) per leaf: back job
+// i goes to wave i mod G; other jobs are left to k_leaf_mixed.
+__global__ __launch_bounds__(64) void k_leaf_dense(const Leaf* __restrict__ leaves,
+                                                   uint64_t leaf_cap, uint64_t* out, Control* ctl) {
+  __shared__ uint16_t list[kWaveList];
+  __shared__ uint32_t mask[kWaveMaskWords];
+  __shared__ uint32_t bases[kWaveBases];
+  const uint64_t counts = uniform64(ctl->leaf_counts);
+  const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
+  if (front + back > leaf_cap) return;  // reported by k_leaf_mixed
+  for (uint64_t i = blockIdx.x; i < back; i += gridDim.x) {
+    const Leaf* rec = leaves + (leaf_cap - 1 - i);
+    Leaf L;
+    L.id = uniform64(rec->id);
+    L.lo = uniform64(rec->lo);
+    L.Nv = uniform64(rec->Nv);
+    L.off = uniform64(rec->off);
+    L.seed = uniform64(rec->seed);
+    L.nv = __builtin_amdgcn_readfirstlane(rec->nv);
+    L.flags = __builtin_amdgcn_readfirstlane(rec->flags);
+    if (!dense_by_wave(L) || L.nv == 0) continue;
+    leaf_dense_wave(L, out, list, mask, bases);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1308,6 +1508,15 @@ int leaf_occupancy() {
   return occ;
 }
 
+int dense_occupancy() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_leaf_dense), 64, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 8;
+  return occ;
+}
+
 int bern_occupancy() {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -1345,6 +1554,12 @@ hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, ui
   else
     hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                        leaf_cap, out, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                             uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_leaf_dense, dim3(grid), dim3(64), 0, stream, leaves, leaf_cap, out, ctl);
   return hipGetLastError();
 }
 

@@ -81,6 +81,8 @@ hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, h
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream);
 // Resident leaf work-groups per compute unit.
 int leaf_occupancy();
+// Resident k_leaf_dense work-groups (one wave each) per compute unit.
+int dense_occupancy();
 // Resident Bernoulli work-groups per compute unit.
 int bern_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
@@ -95,6 +97,10 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
 // (sparse leaves over power-of-two ranges), else the back list (all others).
 hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream);
+// Dense leaves of the back list whose range fits 16-bit positions, one wave
+// per leaf (k_leaf_mixed skips them).
+hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                             uint32_t grid, hipStream_t stream);
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,

@@ -5,6 +5,8 @@ seconds (several leaves, ragged tails, every leaf kind); the 8 GiB
 configuration is compared on windows the oracle computes on its own, plus
 properties that hold at any size.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -36,6 +38,10 @@ WOR_CASES = [
     # sorting window of a leaf, power-of-two and other leaf ranges
     (1 << 22, 1 << 28, 21, 4096, 16),
     (1 << 22, 3 * 2**26 + 5, 22, 4096, 16),
+    # dense ratio 64: dense leaves over 2^16 (one wave each) and 2^17
+    # (work-group path) in one sample
+    (1 << 17, 1 << 22, 23, 4096, 64),
+    (3000, 3000 * 64, 24, 4096, 64),          # one dense leaf over more than 2^16
 ]
 
 
@@ -49,6 +55,43 @@ def test_without_replacement_matches_oracle(ref, n, N, seed, n0, dr):
     got = to_np_u64(out)
     want = ref.sample(n, N, seed, n0=n0, dense_ratio=dr)
     assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def dense_hits(ref, seed, nv, Nv, attempt=0):
+    """Bernoulli hits of the dense root leaf (node 1) of an (nv, Nv) sample,
+    from the oracle's stream words and logarithm (seed finder for the test
+    below)."""
+    rho_num = nv + 3 * math.isqrt(nv) + 8
+    rho = np.float32(rho_num) / np.float32(Nv)
+    cg = np.float32(1.0 / ref.log64(1.0 - float(rho)))
+    u = np.array([ref.u32_geom(ref.stream_word(seed, 1, 3, attempt, t))
+                  for t in range(2 * rho_num)], dtype=np.float32)
+    g = np.floor(ref.log32_batch(u) * cg).astype(np.int64)
+    pos = np.cumsum(g + 1) - 1
+    assert pos[-1] >= Nv, "draw more words"
+    return int(np.count_nonzero(pos < Nv))
+
+
+def test_dense_leaf_beyond_stored_chunks(ref):
+    """One dense leaf whose hit count exceeds the 4352 positions a wave keeps
+    in LDS: the chunks past them are recomputed from their start."""
+    m = dcs()
+    nv, Nv = 4095, 4095 * 16
+    found = []
+    for seed in range(1, 400):
+        c = dense_hits(ref, seed, nv, Nv)
+        if 4352 < c <= 2 * 4096 + 64:
+            found.append((seed, c))
+            if len(found) == 3:
+                break
+    assert found, "no seed with more than 4352 hits"
+    for seed, c in found:
+        announce(f"dense leaf nv={nv} Nv={Nv} seed={seed} hits={c}")
+        out = m.sample(nv, Nv, seed)
+        m.synchronize()
+        got = to_np_u64(out)
+        want = ref.sample(nv, Nv, seed)
+        assert np.array_equal(got, want), first_mismatch(got, want)
 
 
 def test_config1_invariants_and_repeatability():
