@@ -191,6 +191,19 @@ __device__ __forceinline__ float series32(float z) {
   return 1.0f / 3.0f + z * p;
 }
 
+// f / d for |f| < 1/2 and d in [3/2, 5/2] (the logarithm's reduced
+// argument): no operand scaling or special case can arise, so a hardware
+// reciprocal refined by one Newton step, the product, and one correction
+// from the exact (fused) residual give the correctly rounded quotient -- for
+// every f the reduction can produce, which a test checks against the
+// correctly rounded division.
+__device__ __forceinline__ float div_reduced(float f, float d) {
+  float y = __builtin_amdgcn_rcpf(d);
+  y = __builtin_fmaf(__builtin_fmaf(-d, y, 1.0f), y, y);
+  const float q = f * y;
+  return __builtin_fmaf(__builtin_fmaf(-q, d, f), y, q);
+}
+
 __device__ __forceinline__ float log32(float x) {
   const uint32_t bits = __float_as_uint(x);
   int e = static_cast<int>((bits >> 23) & 0xFF) - 127;
@@ -200,7 +213,7 @@ __device__ __forceinline__ float log32(float x) {
     e += 1;
   }
   const float f = m - 1.0f;
-  const float s = f / (2.0f + f);
+  const float s = div_reduced(f, 2.0f + f);
   const float z = s * s;
   const float t = s + s;
   const float r = t + t * (z * series32(z));

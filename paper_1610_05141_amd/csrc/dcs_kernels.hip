@@ -132,8 +132,8 @@ constexpr uint32_t kSpareSlot = kRegionA - 1;
 static_assert(kSpareSlot >= kKeys, "spare slot lies outside the sorted keys");
 constexpr uint32_t kSmemWords = kRegionA + kRegionB + kCacheWords + kScratch;
 // scratch words: [0, 16) scan; 16 next-word offset; 17 duplicate flag;
-// [24, 40) per-wave maxima
-constexpr uint32_t kScrNext = 16, kScrDups = 17, kScrMax = 24;
+// [24, 40) per-wave maxima; 48 which cached jobs the work-group runs
+constexpr uint32_t kScrNext = 16, kScrDups = 17, kScrMax = 24, kScrKeep = 48;
 
 __device__ __forceinline__ uint32_t bpad(uint32_t b) { return b + (b >> kBucketPad); }
 
@@ -793,9 +793,10 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long m) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
 }
 
-// Chunk c of the skip stream: lane l holds draws 256c + 4l + j (j < 4).  On
-// return q[j] is the 1-based position reached after draw j (the hit, if
-// q[j] <= Nv, sits at q[j] - 1) and the result is the chunk's total advance.
+// Chunk c of the skip stream: lane l holds draws 256c + 4l + j (j < 4), the
+// words of Philox block 64c + l.  On return q[j] is the 1-based position
+// reached after draw j (the hit, if q[j] <= Nv, sits at q[j] - 1) and the
+// result is the chunk's total advance.
 __device__ __forceinline__ uint32_t skip_chunk(const Stream& st, uint32_t c, uint32_t lane,
                                                float cg, uint32_t q_base, uint32_t q[4]) {
   const uint4 w = philox_block(st, c * (kWaveChunk / 4) + lane);
@@ -814,6 +815,15 @@ __device__ __forceinline__ uint32_t skip_chunk(const Stream& st, uint32_t c, uin
     q[j] = x;
   }
   return __builtin_amdgcn_readlane(incl, 63);
+}
+
+// The chunk's four positions q[j] - 1 as 16-bit values (entries past the
+// last hit are never read).
+__device__ __forceinline__ void put_chunk(uint16_t* dst, const uint32_t q[4]) {
+  uint2 v;
+  v.x = ((q[0] - 1u) & 0xFFFFu) | ((q[1] - 1u) << 16);
+  v.y = ((q[2] - 1u) & 0xFFFFu) | ((q[3] - 1u) << 16);
+  *reinterpret_cast<uint2*>(dst) = v;
 }
 
 // One wave samples one dense leaf (Algorithm B, Sec. 2, with geometric skips,
@@ -849,11 +859,7 @@ __device__ void leaf_dense_wave(const Leaf& L, uint64_t* out, uint16_t* list, ui
         uint32_t in = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) in += q[j] <= Nv ? 1u : 0u;
-        if (c < kWaveListChunks) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (q[j] <= Nv) list[c * kWaveChunk + 4u * lane + j] = static_cast<uint16_t>(q[j] - 1u);
-        }
+        if (c < kWaveListChunks) put_chunk(list + c * kWaveChunk + 4u * lane, q);
         // hits are a prefix of the chunk: whole lanes, then one partial lane
         const unsigned long long whole = __ballot(in == 4u);
         const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
@@ -925,9 +931,7 @@ __device__ void leaf_dense_wave(const Leaf& L, uint64_t* out, uint16_t* list, ui
         if (c >= kWaveListChunks && (k0 % kWaveChunk) == 0) {
           uint32_t q[4];
           skip_chunk(st, c, lane, cg, bases[c], q);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (q[j] <= Nv) list[kSpare + 4u * lane + j] = static_cast<uint16_t>(q[j] - 1u);
+          put_chunk(list + kSpare + 4u * lane, q);
         }
         const uint32_t slot = c < kWaveListChunks ? k : kSpare + (k - c * kWaveChunk);
         if (k < cnt) pos = list[slot];
@@ -981,6 +985,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
     zero_counters<B>(sm.buck, threadIdx.x);
     __syncthreads();
   }
+  uint32_t keep = ~0u;  // bit s: cached job s is run here (not by k_leaf_dense)
   for (uint64_t j = 0;; ++j) {
     const uint64_t i = blockIdx.x + j * G;
     if (i >= n_leaves) break;
@@ -1001,7 +1006,28 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
         }
       }
       __syncthreads();
+      if constexpr (!kPow2) {
+        if (tid < 64) {
+          bool run = false;
+          if (tid < kCacheLeaves && i + static_cast<uint64_t>(tid) * G < n_leaves) {
+            Leaf c;
+            const uint32_t* r = cache + tid * kLeafWords;
+            c.Nv = static_cast<uint64_t>(r[4]) | (static_cast<uint64_t>(r[5]) << 32);
+            c.flags = r[11];
+            run = !dense_by_wave(c);
+          }
+          const unsigned long long m = __ballot(run);
+          if (tid == 0) sm.scr[kScrKeep] = static_cast<uint32_t>(m);
+        }
+        __syncthreads();
+        keep = __builtin_amdgcn_readfirstlane(sm.scr[kScrKeep]);
+        if (keep == 0) {  // the whole group is k_leaf_dense's
+          j += kCacheLeaves - 1;
+          continue;
+        }
+      }
     }
+    if (!kPow2 && !((keep >> slot) & 1u)) continue;  // k_leaf_dense's
     Leaf L;
     {
       const uint4* c = reinterpret_cast<const uint4*>(cache + slot * kLeafWords);
@@ -1030,7 +1056,6 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
       // barrier, which every thread reaches only after its output pass.
       leaf_sparse_pow2<B>(L, out, sm);
     } else {
-      if (dense_by_wave(L)) continue;  // k_leaf_dense's
       switch (L.flags & 3u) {
         case kKindSparse: leaf_sparse<B>(L, out, sm); break;
         case kKindDense: leaf_dense<B>(L, out, sm); break;
@@ -1058,7 +1083,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
 // i goes to wave i mod G; other jobs are left to k_leaf_mixed.
 __global__ __launch_bounds__(64) void k_leaf_dense(const Leaf* __restrict__ leaves,
                                                    uint64_t leaf_cap, uint64_t* out, Control* ctl) {
-  __shared__ uint16_t list[kWaveList];
+  __shared__ __align__(16) uint16_t list[kWaveList];
   __shared__ uint32_t mask[kWaveMaskWords];
   __shared__ uint32_t bases[kWaveBases];
   const uint64_t counts = uniform64(ctl->leaf_counts);

@@ -74,18 +74,23 @@ def dense_hits(ref, seed, nv, Nv, attempt=0):
 
 def test_dense_leaf_beyond_stored_chunks(ref):
     """One dense leaf whose hit count exceeds the 4352 positions a wave keeps
-    in LDS: the chunks past them are recomputed from their start."""
+    in LDS: the chunk past them is recomputed from its start (the seeds with
+    the most hits among the first 40, and one just below the bound)."""
     m = dcs()
     nv, Nv = 4095, 4095 * 16
-    found = []
-    for seed in range(1, 400):
+    counts = [(dense_hits(ref, seed, nv, Nv), seed) for seed in range(1, 41)]
+    counts.sort(reverse=True)
+    found = [(nv, seed, c) for c, seed in counts[:3]]
+    assert found[-1][2] > 4352, counts
+    # a leaf whose hits just fit the stored chunks
+    for seed in range(41, 400):
         c = dense_hits(ref, seed, nv, Nv)
-        if 4352 < c <= 2 * 4096 + 64:
-            found.append((seed, c))
-            if len(found) == 3:
-                break
-    assert found, "no seed with more than 4352 hits"
-    for seed, c in found:
+        if 4352 - 8 <= c <= 4352:
+            found.append((nv, seed, c))
+            break
+    assert found[-1][2] <= 4352, found
+    for nv, seed, c in found:
+        Nv = nv * 16
         announce(f"dense leaf nv={nv} Nv={Nv} seed={seed} hits={c}")
         out = m.sample(nv, Nv, seed)
         m.synchronize()
