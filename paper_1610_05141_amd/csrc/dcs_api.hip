@@ -211,6 +211,7 @@ int32_t device_ctx(DeviceCtx** out) {
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
     c.bern_occupancy = dcs::bern_occupancy();
+    c.bern_wave_occupancy = dcs::bern_wave_occupancy();
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
 
@@ -365,7 +366,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
 }
 
 struct BernLayout {
-  size_t ctl = 0, status = 0, total = 0;
+  size_t ctl = 0, tickets = 0, status = 0, total = 0;
 };
 
 BernLayout bern_layout(uint64_t n_chunks) {
@@ -373,6 +374,8 @@ BernLayout bern_layout(uint64_t n_chunks) {
   size_t o = 0;
   L.ctl = o;
   o = align_up(o + sizeof(Control));
+  L.tickets = o;
+  o = align_up(o + sizeof(unsigned long long) * dcs::kTicketWords);
   L.status = o;
   o = align_up(o + sizeof(unsigned long long) * n_chunks);
   L.total = o;
@@ -448,20 +451,22 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(base + L.status);
+  unsigned long long* tickets = reinterpret_cast<unsigned long long*>(base + L.tickets);
   const double c64 = 1.0 / host_log1p_series(-p);
   const float c32 = static_cast<float>(c64);
   const int fp32 = p >= 0x1p-10 ? 1 : 0;
   Timing t0{}, t1{};
   timing_begin(0, s, &t0);
-  hipError_t e = dcs::launch_zero(ctl, status, n_chunks, s);
+  hipError_t e = dcs::launch_zero(ctl, status, n_chunks, tickets, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
+  const uint64_t occ = static_cast<uint64_t>(fp32 ? c->bern_wave_occupancy : c->bern_occupancy);
   const uint32_t grid = static_cast<uint32_t>(
-      std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->bern_occupancy)));
+      std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * occ)));
   const uint32_t lds_cap = 2 * P.n0 + 64;
   timing_begin(3, s, &t1);
   e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,
-                            count_dev, ctl, grid, lds_cap, s);
+                            count_dev, ctl, tickets, grid, lds_cap, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
   g_ctl_used.insert(ctl);

@@ -46,6 +46,7 @@ struct DeviceCtx {
   int cus = 256;
   int leaf_occupancy = 2;
   int bern_occupancy = 2;
+  int bern_wave_occupancy = 8;
   int dense_occupancy = 8;
   // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
   // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut;

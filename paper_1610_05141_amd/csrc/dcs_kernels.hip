@@ -1254,10 +1254,12 @@ __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance*
   }
 }
 
-__global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n) {
+__global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n,
+                       unsigned long long* tickets) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     status[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kTicketWords) tickets[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->leaf_counts = 0;
     ctl->chunk_ticket = 0;
@@ -1274,55 +1276,39 @@ constexpr unsigned long long kValueMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 26;
 constexpr uint32_t kBernLds = kRegionA;  // holds lds_cap = 2 n0 + 64 <= 8256 offsets
 
-// One pass over the chunk's geometric stream.  Hit k of the chunk sits at
+// Double-precision Bernoulli chunks (p < 2^-10), one work-group per chunk:
+// one pass over the chunk's geometric stream.  Hit k of the chunk sits at
 // 1-based offset q_k = sum_{i<=k} (skip_i + 1); draws are taken in (round,
-// thread, word) order, so each round's offsets come from one block scan.  Hits
+// thread, draw) order, so each round's offsets come from one block scan.  Hits
 // k < lds_cap go to pos[] when write == false; when write == true, hits
 // k >= lds_cap are written straight to out (the chunk held more hits than LDS).
-// Returns the chunk's hit count.
-//   F32: p >= 2^-10, the chunk has at most 2^22 positions and a skip is at
-//        most 22.2/p < 2^15, so offsets and round sums fit 32 bits.
-//   F64: skips are capped at 2^33 (anything that long ends the chunk).
-template <bool F32>
-__device__ uint64_t bern_pass(const Stream& st, uint64_t len, double c64, float c32,
-                              uint32_t* pos, uint32_t lds_cap, bool write, uint64_t* out,
-                              uint64_t out_first, uint64_t capacity, uint64_t base,
-                              uint64_t* scr64, uint32_t* scr, uint32_t* ends) {
+// Skips are capped at 2^33 (anything that long ends the chunk).  Returns the
+// chunk's hit count.
+__device__ uint64_t bern_pass(const Stream& st, uint64_t len, double c64, uint32_t* pos,
+                              uint32_t lds_cap, bool write, uint64_t* out, uint64_t out_first,
+                              uint64_t capacity, uint64_t base, uint64_t* scr64, uint32_t* ends) {
   constexpr int B = kBernBlock;
-  constexpr uint32_t per = F32 ? 4u : 2u;
-  using Acc = typename std::conditional<F32, uint32_t, uint64_t>::type;
+  constexpr uint32_t per = 2u;
   const uint32_t tid = threadIdx.x;
-  const Acc lim = static_cast<Acc>(len);
-  Acc last = 0;  // offset of the previous round's last draw
+  const uint64_t lim = len;
+  uint64_t last = 0;  // offset of the previous round's last draw
   uint64_t count = 0;
   for (uint32_t blk0 = 0;; blk0 += B) {
     const uint4 w = philox_block(st, blk0 + tid);
-    Acc inc[per];
-    Acc sum = 0;
-    if constexpr (F32) {
+    uint64_t inc[per];
+    uint64_t sum = 0;
+    const uint64_t d0 = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
+    const uint64_t d1 = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
 #pragma unroll
-      for (uint32_t j = 0; j < per; ++j) {
-        inc[j] = static_cast<uint32_t>(geom_skip32(pick(w, j), c32)) + 1u;
-        sum += inc[j];
-      }
-    } else {
-      const uint64_t d0 = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
-      const uint64_t d1 = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
-#pragma unroll
-      for (uint32_t j = 0; j < per; ++j) {
-        const double g = floor(log64(unit_open0(j ? d1 : d0)) * c64);
-        const double gc = g < 0x1p33 ? g : 0x1p33;
-        inc[j] = static_cast<uint64_t>(gc) + 1;
-        sum += inc[j];
-      }
+    for (uint32_t j = 0; j < per; ++j) {
+      const double g = floor(log64(unit_open0(j ? d1 : d0)) * c64);
+      const double gc = g < 0x1p33 ? g : 0x1p33;
+      inc[j] = static_cast<uint64_t>(gc) + 1;
+      sum += inc[j];
     }
-    Acc total;
-    Acc q0;
-    if constexpr (F32)
-      q0 = last + block_scan_excl<B, uint32_t>(sum, scr, &total);
-    else
-      q0 = last + block_scan_excl<B, uint64_t>(sum, scr64, &total);
-    Acc q = q0;
+    uint64_t total;
+    const uint64_t q0 = last + block_scan_excl<B, uint64_t>(sum, scr64, &total);
+    uint64_t q = q0;
     const bool all_in = last + total <= lim;
     const uint64_t first_idx = count + per * tid;
     uint32_t in = 0;
@@ -1407,14 +1393,12 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
   return acc;
 }
 
-template <bool F32>
 __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
-                                                     uint64_t n_chunks, double c64, float c32,
+                                                     uint64_t n_chunks, double c64,
                                                      unsigned long long* status, uint64_t* out,
                                                      uint64_t capacity, uint64_t* count_dev,
                                                      Control* ctl, uint32_t lds_cap) {
   __shared__ uint32_t pos[kBernLds];
-  __shared__ uint32_t scr[32];
   __shared__ uint64_t scr64[8];
   __shared__ uint32_t ends;
   __shared__ unsigned long long cur, excl;
@@ -1427,8 +1411,8 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
     const uint64_t base = j * chunk;
     const uint64_t len = (N - base) < chunk ? (N - base) : chunk;
     const Stream st = make_stream(seed, j, kBChunk, 0);
-    const uint64_t cnt = bern_pass<F32>(st, len, c64, c32, pos, lds_cap, false, out, 0, capacity,
-                                        base, scr64, scr, &ends);
+    const uint64_t cnt =
+        bern_pass(st, len, c64, pos, lds_cap, false, out, 0, capacity, base, scr64, &ends);
     if (threadIdx.x < 64) {
       const uint64_t acc = bern_lookback(status, j, cnt, ctl);
       if (threadIdx.x == 0) {
@@ -1445,9 +1429,110 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
     for (uint64_t i = threadIdx.x; i < held; i += kBernBlock)
       if (first + i < capacity) store_out(out + first + i, base + static_cast<uint64_t>(pos[i]) + 1);
     if (cnt > lds_cap)
-      bern_pass<F32>(st, len, c64, c32, pos, lds_cap, true, out, first, capacity, base, scr64,
-                     scr, &ends);
+      bern_pass(st, len, c64, pos, lds_cap, true, out, first, capacity, base, scr64, &ends);
     __syncthreads();
+  }
+}
+
+// Single-precision Bernoulli chunks (p >= 2^-10), one wave per chunk and no
+// barrier: chunk j's hits are its draws up to the one that passes the chunk
+// end (Sec. 4.7's skips); the wave keeps their increments, which are below
+// 22.2/p + 1 < 2^16, as 16-bit values (the first kBernWaveList of them;
+// later 256-draw groups are recomputed when written), publishes its count for
+// the look-back, and writes the positions as a running sum, consecutive lanes
+// on consecutive outputs.
+constexpr uint32_t kBernWaveGroup = 256;                     // draws per group
+constexpr uint32_t kBernWaveGroups = 16;                     // groups kept in LDS
+constexpr uint32_t kBernWaveList = kBernWaveGroup * kBernWaveGroups;
+
+// Increments of draw group c (lane l: draws 256c + 4l + j) into dst, and
+// their wave-wide inclusive prefix over lanes.
+__device__ __forceinline__ uint32_t bern_group(const Stream& st, uint32_t c, uint32_t lane,
+                                               float c32, uint32_t inc[4]) {
+  const uint4 w = philox_block(st, c * (kBernWaveGroup / 4) + lane);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    inc[j] = static_cast<uint32_t>(geom_skip32(pick(w, j), c32)) + 1u;
+    sum += inc[j];
+  }
+  return sum;
+}
+
+__device__ __forceinline__ void put_incs(uint16_t* dst, const uint32_t inc[4]) {
+  uint2 v;
+  v.x = inc[0] | (inc[1] << 16);
+  v.y = inc[2] | (inc[3] << 16);
+  *reinterpret_cast<uint2*>(dst) = v;
+}
+
+__global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uint64_t chunk,
+                                                  uint64_t n_chunks, float c32,
+                                                  unsigned long long* status, uint64_t* out,
+                                                  uint64_t capacity, uint64_t* count_dev,
+                                                  Control* ctl, unsigned long long* tickets,
+                                                  uint32_t n_cls) {
+  __shared__ __align__(16) uint16_t list[kBernWaveList];
+  const uint32_t lane = lane_tid();
+  constexpr uint32_t kSpare = (kBernWaveGroups - 1) * kBernWaveGroup;  // recomputed groups
+  // Chunks are handed out by n_cls counters, 256 bytes apart: this wave's
+  // class c = blockIdx mod n_cls takes chunks c, c + n_cls, ... in order.
+  // Same-address atomics serialize, so one shared counter would cap the
+  // chunk rate; with n_cls coprime to the 8 XCDs that work-groups alternate
+  // over, any n_cls work-groups on one XCD cover every class, so a chunk not
+  // yet handed out always has a running wave that will take it (which the
+  // look-back's progress needs).
+  const uint32_t cls = blockIdx.x % n_cls;
+  unsigned long long* const ticket = tickets + cls * kTicketStride;
+  for (;;) {
+    uint64_t jt = 0;
+    if (lane == 0) jt = atomicAdd(ticket, 1ull);
+    const uint64_t j = cls + uniform64(jt) * n_cls;
+    if (j >= n_chunks) break;
+    const uint64_t base = j * chunk;
+    const uint32_t len = static_cast<uint32_t>((N - base) < chunk ? (N - base) : chunk);
+    const Stream st = make_stream(seed, j, kBChunk, 0);
+    // hits: the draws whose running position stays within the chunk
+    uint32_t q_base = 0, cnt = 0;
+    for (uint32_t c = 0;; ++c) {
+      uint32_t inc[4];
+      const uint32_t sum = bern_group(st, c, lane, c32, inc);
+      const uint32_t incl = wave_scan_incl(sum);
+      uint32_t q = q_base + incl - sum;
+      uint32_t in = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        q += inc[k];
+        in += q <= len ? 1u : 0u;
+      }
+      if (c < kBernWaveGroups) put_incs(list + c * kBernWaveGroup + 4u * lane, inc);
+      const unsigned long long whole = __ballot(in == 4u);
+      const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+      const uint32_t got = nw == 64u ? kBernWaveGroup : 4u * nw + __builtin_amdgcn_readlane(in, nw);
+      cnt += got;
+      q_base += __builtin_amdgcn_readlane(incl, 63);
+      if (got < kBernWaveGroup) break;
+    }
+    const uint64_t first = bern_lookback(status, j, cnt, ctl);
+    if (lane == 0 && j == n_chunks - 1) {
+      *count_dev = first + cnt;
+      ctl->bern_count = first + cnt;
+    }
+    uint32_t qb = 0;
+    for (uint32_t k0 = 0; k0 < cnt; k0 += 64u) {
+      const uint32_t c = k0 / kBernWaveGroup;
+      if (c >= kBernWaveGroups && (k0 % kBernWaveGroup) == 0) {
+        uint32_t inc[4];
+        bern_group(st, c, lane, c32, inc);
+        put_incs(list + kSpare + 4u * lane, inc);
+      }
+      const uint32_t k = k0 + lane;
+      const uint32_t slot = c < kBernWaveGroups ? k : kSpare + (k - c * kBernWaveGroup);
+      const uint32_t inc = k < cnt ? static_cast<uint32_t>(list[slot]) : 0u;
+      const uint32_t incl = wave_scan_incl(inc);
+      if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + incl);
+      qb += __builtin_amdgcn_readlane(incl, 63);
+    }
   }
 }
 
@@ -1516,11 +1601,13 @@ hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, h
   return hipGetLastError();
 }
 
-hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream) {
+hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
+                       unsigned long long* tickets, hipStream_t stream) {
   uint64_t blocks = (n + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_zero, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, status, n);
+  hipLaunchKernelGGL(k_zero, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, status, n,
+                     tickets);
   return hipGetLastError();
 }
 
@@ -1542,10 +1629,19 @@ int dense_occupancy() {
   return occ;
 }
 
+int bern_wave_occupancy() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_bern_wave), 64, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 8;
+  return occ;
+}
+
 int bern_occupancy() {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &occ, reinterpret_cast<const void*>(k_bern<true>), kBernBlock, 0) != hipSuccess ||
+          &occ, reinterpret_cast<const void*>(k_bern), kBernBlock, 0) != hipSuccess ||
       occ <= 0)
     occ = 2;
   return occ;
@@ -1591,14 +1687,16 @@ hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* ou
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks,
                             int fp32, double c64, float c32, unsigned long long* status,
                             uint64_t* out, uint64_t capacity, uint64_t* count_dev, Control* ctl,
-                            uint32_t grid, uint32_t lds_cap, hipStream_t stream) {
+                            unsigned long long* tickets, uint32_t grid, uint32_t lds_cap,
+                            hipStream_t stream) {
   (void)p;
+  const uint32_t n_cls = grid < kTicketClasses ? grid : kTicketClasses;
   if (fp32)
-    hipLaunchKernelGGL(k_bern<true>, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk,
-                       n_chunks, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
+    hipLaunchKernelGGL(k_bern_wave, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
+                       status, out, capacity, count_dev, ctl, tickets, n_cls);
   else
-    hipLaunchKernelGGL(k_bern<false>, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk,
-                       n_chunks, c64, c32, status, out, capacity, count_dev, ctl, lds_cap);
+    hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk, n_chunks,
+                       c64, status, out, capacity, count_dev, ctl, lds_cap);
   return hipGetLastError();
 }
 

@@ -71,20 +71,29 @@ constexpr int kLeafBlock = 512;             // threads of a leaf work-group
 constexpr int kBernBlock = 256;             // threads of a Bernoulli work-group
 constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
 constexpr uint64_t kFillPiece = 1ull << 16; // constant-fill leaves are cut to this
+// Single-precision Bernoulli chunks are handed out by kTicketClasses
+// counters (7: coprime to the 8 XCDs), kTicketStride words apart.
+constexpr uint32_t kTicketClasses = 7;
+constexpr uint32_t kTicketStride = 32;
+constexpr uint32_t kTicketWords = kTicketClasses * kTicketStride;
 
 // Kernel launchers (defined in dcs_kernels.hip).
 // Zero the counters of a control block (the error word is kept: it is
 // sticky until the host reads and clears it); if `single` is non-null, also
 // store that instance as entry 0 of the instance table.
 hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, hipStream_t stream);
-// launch_reset for a Bernoulli call plus zeroing of its look-back status words.
-hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n, hipStream_t stream);
+// launch_reset for a Bernoulli call plus zeroing of its look-back status words
+// and its kTicketWords chunk counters.
+hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
+                       unsigned long long* tickets, hipStream_t stream);
 // Resident leaf work-groups per compute unit.
 int leaf_occupancy();
 // Resident k_leaf_dense work-groups (one wave each) per compute unit.
 int dense_occupancy();
-// Resident Bernoulli work-groups per compute unit.
+// Resident work-groups per compute unit of the double-precision Bernoulli
+// kernel, and of the one-wave single-precision one.
 int bern_occupancy();
+int bern_wave_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
 // frontier (written to `frontier`, one slot per top thread).
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
@@ -104,8 +113,8 @@ hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* ou
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,
-                            uint64_t* count_dev, Control* ctl, uint32_t grid,
-                            uint32_t lds_cap, hipStream_t stream);
+                            uint64_t* count_dev, Control* ctl, unsigned long long* tickets,
+                            uint32_t grid, uint32_t lds_cap, hipStream_t stream);
 hipError_t launch_bernoulli_fill(uint64_t N, uint64_t* out, uint64_t capacity,
                                  uint64_t* count_dev, hipStream_t stream);
 hipError_t launch_debug(int op, const void* x, const void* x2, void* y, uint64_t count,

@@ -147,6 +147,9 @@ BERN_CASES = [
     (0.0, 1000, 5),
     (1.0, 1000, 6),
     (0.5, 3, 7),
+    # chunks of 8192 with ~4096 hits: about half hold more hits than the
+    # 4096 increments a wave keeps, and recompute their last group
+    (0.5, 1 << 22, 21),
 ]
 
 
