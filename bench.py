@@ -303,7 +303,7 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage_ms, stage_n = dcs.profile_read(2)
-    leaf_ms, leaf_n = dcs.profile_read(4)     # the power-of-two sparse leaf kernel
+    leaf_ms, leaf_n = dcs.profile_read(4)     # the power-of-two leaf kernel
     mixed_ms, mixed_n = dcs.profile_read(5)   # work-group leaf kernel of the other kinds
     dense_ms, dense_n = dcs.profile_read(6)   # one-wave dense leaf kernel
     tree_ms, tree_n = dcs.profile_read(1)

@@ -243,7 +243,8 @@ const char* dcs_status_string(int32_t status);
  * dcs_profile_read: after the stream is synchronized, accumulated
  * milliseconds and launch count for kernel `kind`
  * (0 = reset, 1 = tree split, 2 = leaf stage: all three leaf kernels,
- * 3 = Bernoulli chunk, 4 = leaf kernel of the sparse power-of-two jobs,
+ * 3 = Bernoulli chunk, 4 = leaf kernel of the sparse and with-replacement
+ * jobs over power-of-two ranges,
  * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
  * kernel of the dense jobs with ranges up to 2^16); DCS_EINVAL for another
  * kind. */

@@ -282,8 +282,9 @@ def tune_reset() -> None:
 
 def profile_read(kind: int):
     """(total milliseconds, launches) of kernel kind 0 reset, 1 tree, 2 leaf
-    stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse
-    power-of-two jobs, 5 work-group leaf kernel of the other jobs, 6
+    stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse and
+    with-replacement jobs over power-of-two ranges, 5 work-group leaf kernel
+    of the other jobs, 6
     one-wave dense leaf kernel, accumulated since profile_enable (read after
     synchronize)."""
     ms = ctypes.c_double(0)

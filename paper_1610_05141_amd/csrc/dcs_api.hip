@@ -192,7 +192,7 @@ std::set<void*> g_ctl_used;  // control blocks to check at synchronize
 bool g_profile = false;
 std::vector<Timing> g_timings;
 // kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
-// 4 leaf kernel of the power-of-two sparse list, 5 work-group leaf kernel of
+// 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
 // the rest, 6 one-wave dense leaf kernel
 constexpr int kProfKinds = 7;
 double g_prof_ms[kProfKinds] = {};

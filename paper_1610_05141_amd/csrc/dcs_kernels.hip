@@ -352,9 +352,13 @@ __device__ __forceinline__ void zero_counters(uint32_t* cnt, uint32_t tid) {
   if (tid == 0) cnt[kSpareCount] = 0;
 }
 
-template <int B, bool kLazyZero = false>
+constexpr uint32_t kDeadKey = 0xFFFFFFFFu;  // counter/slot word of a key left out
+
+// kMasked: key[q] takes part iff bit q of `live` is set (n of them), wherever
+// it sits; otherwise key[q] takes part iff its position 4(tid + kB) + j < n.
+template <int B, bool kLazyZero = false, bool kMasked = false>
 __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n, uint32_t shift,
-                                   uint32_t nb, LeafSmem& sm) {
+                                   uint32_t nb, LeafSmem& sm, uint32_t live_mask = 0) {
   constexpr int kBlk = kKeys / (4 * B);
   constexpr int kPer = kBuckets / B;  // buckets per thread in the scan
   constexpr int kPairs = kKeys / (2 * B);
@@ -375,7 +379,19 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
     const uint32_t first = 4 * (wave_first + k * B);  // first key position of the wave
-    if (first + 256 <= n) {                           // every lane holds 4 keys
+    if (kMasked) {
+      // dead keys skip the counters and the scatter (all of them on one
+      // spare word would serialize the LDS accesses of the whole wave)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = 4 * k + j;
+        as[q] = kDeadKey;
+        if ((live_mask >> q) & 1u) {
+          const uint32_t a = bpad(key[q] >> shift);
+          as[q] = a | (atomicAdd(&cnt[a], 1u) << 16);
+        }
+      }
+    } else if (first + 256 <= n) {                    // every lane holds 4 keys
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int q = 4 * k + j;
@@ -427,7 +443,13 @@ __device__ uint32_t sort_registers(const uint32_t (&key)[kKeys / B], uint32_t n,
   // 3. scatter in bucket order (unused positions land on the spare slot)
 #pragma unroll
   for (int k = 0; k < kBlk; ++k) {
-    if (4 * (wave_first + k * B) < n) {
+    if (kMasked) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = 4 * k + j;
+        if (as[q] != kDeadKey) keys[cnt[as[q] & 0xFFFFu] + (as[q] >> 16)] = key[q];
+      }
+    } else if (4 * (wave_first + k * B) < n) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int q = 4 * k + j;
@@ -603,20 +625,91 @@ __device__ void sparse_rounds(const Stream& st, uint64_t t, uint32_t have, uint3
   }
 }
 
+// First round of a sparse or with-replacement leaf over a range that is not a
+// power of two, in registers: the words t < W of the stream mapped into
+// [0, N_v), W = n_v plus twice the expected number of void words among n_v,
+// plus 32 (at most 4096); the first
+// n_v non-void values in stream order are the live keys (bit q of *live for
+// key[q]), ranked by one block scan.  Returns how many of the W words are
+// non-void (below n_v the caller takes the LDS rounds instead); when it is at
+// least n_v, sm.scr[kScrNext] holds the word index just after the n_v-th
+// value once a barrier has passed.
+template <int B>
+__device__ uint32_t first_round_regs(const Stream& st, uint32_t nv, const RangeInfo& ri,
+                                     uint32_t (&key)[kKeys / B], uint32_t* live, LeafSmem& sm) {
+  constexpr int kBlk = kKeys / (4 * B);
+  static_assert(kBlk == 2, "two 16-bit counts share one scanned word");
+  const uint32_t tid = lane_tid();
+  const uint64_t extra = ((2ull * nv * ri.thr) >> 32) + 32u;
+  const uint32_t W = nv + extra < kKeys ? nv + static_cast<uint32_t>(extra) : kKeys;
+  const uint32_t nblk = (W + 3) >> 2;
+  uint32_t ok = 0;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) key[4 * k + j] = 0;
+    if (blk < nblk) {
+      const uint4 w = philox_block(st, blk);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint32_t v;
+        const bool good = range_map(pick(w, j), ri.s, ri.thr, &v);
+        key[4 * k + j] = v;
+        if (good && 4 * blk + j < W) ok |= 1u << (4 * k + j);
+      }
+    }
+  }
+  uint32_t total;
+  const uint32_t packed = static_cast<uint32_t>(__popc(ok & 0xFu)) |
+                          (static_cast<uint32_t>(__popc(ok >> 4)) << 16);
+  const uint32_t excl = block_scan_excl<B, uint32_t>(packed, sm.scr, &total);
+  const uint32_t total0 = total & 0xFFFFu;
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t base = k == 0 ? (excl & 0xFFFFu) : total0 + (excl >> 16);
+    const uint32_t okk = (ok >> (4 * k)) & 0xFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t rank = base + static_cast<uint32_t>(__popc(okk & ((1u << j) - 1u)));
+      if (((okk >> j) & 1u) && rank < nv) {
+        m |= 1u << (4 * k + j);
+        if (rank == nv - 1) sm.scr[kScrNext] = 4 * (tid + k * B) + j + 1;
+      }
+    }
+  }
+  *live = m;
+  return total0 + (total >> 16);
+}
+
 template <int B>
 __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const uint32_t nv = L.nv;
+  if (nv == 0) return;
   const RangeInfo ri = range_info(L.Nv);
   uint32_t shift, nb;
   bucket_params(L.Nv, nv, &shift, &nb);
   const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
-  sparse_rounds<B>(st, 0, 0, nv, ri, shift, nb, sm);
+  uint32_t key[kKeys / B];
+  uint32_t live;
+  if (first_round_regs<B>(st, nv, ri, key, &live, sm) >= nv) {
+    if (sort_registers<B, false, true>(key, nv, shift, nb, sm, live) != 0) {
+      const uint64_t t = sm.scr[kScrNext];
+      const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
+      sparse_rounds<B>(st, t, have, nv, ri, shift, nb, sm);
+    }
+  } else {
+    // too many void words among the first W: the general rounds from word 0
+    sparse_rounds<B>(st, 0, 0, nv, ri, shift, nb, sm);
+  }
   write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
 
-// Sparse leaf on a power-of-two range (no word is void): the first round's
-// n_v words go from Philox straight into registers; the general rounds take
-// over only if a value repeats.
+// Sparse or with-replacement leaf on a power-of-two range (no word is void):
+// the first round's n_v words go from Philox straight into registers; for a
+// sparse leaf the general rounds take over only if a value repeats (a
+// with-replacement leaf keeps repeats).
 template <int B>
 __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   constexpr int kBlk = kKeys / (4 * B);
@@ -626,7 +719,8 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const uint32_t pshift = 32u - kb;                 // value = word >> pshift
   uint32_t shift, nb;
   bucket_params(L.Nv, nv, &shift, &nb);
-  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
+  const bool wr = (L.flags & 3u) == kKindWr;
+  const Stream st = make_stream(L.seed, L.id, wr ? kWrLeaf : kLeaf, 0);
   const uint32_t nblk = (nv + 3) >> 2;
   uint32_t key[kKeys / B];
 #pragma unroll
@@ -640,7 +734,7 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
       key[4 * k + 3] = w.w >> pshift;
     }
   }
-  if (sort_registers<B, true>(key, nv, shift, nb, sm) != 0) {
+  if (sort_registers<B, true>(key, nv, shift, nb, sm) != 0 && !wr) {
     const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
     sparse_rounds<B, true>(st, nv, have, nv, range_info(L.Nv), shift, nb, sm);
   }
@@ -651,17 +745,23 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
 template <int B>
 __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const uint32_t nv = L.nv;
+  if (nv == 0) return;
   const RangeInfo ri = range_info(L.Nv);
   uint32_t shift, nb;
   bucket_params(L.Nv, nv, &shift, &nb);
   const Stream st = make_stream(L.seed, L.id, kWrLeaf, 0);
-  uint32_t* keys = sm.keys;
-  take_values<B>(st, 0, nv, ri, sm.scr, [&](uint32_t p, uint32_t v) { keys[p] = v; });
   uint32_t key[kKeys / B];
-  load_registers<B>(key, keys, nv);
-  __syncthreads();
-  sort_registers<B>(key, nv, shift, nb, sm);
-  write_sorted_pairs<B>(out + L.off, L.lo, keys, nv);
+  uint32_t live;
+  if (first_round_regs<B>(st, nv, ri, key, &live, sm) >= nv) {
+    sort_registers<B, false, true>(key, nv, shift, nb, sm, live);
+  } else {
+    uint32_t* keys = sm.keys;
+    take_values<B>(st, 0, nv, ri, sm.scr, [&](uint32_t p, uint32_t v) { keys[p] = v; });
+    load_registers<B>(key, keys, nv);
+    __syncthreads();
+    sort_registers<B>(key, nv, shift, nb, sm);
+  }
+  write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
 
 // ---------------------------------------------------------------------------
@@ -955,9 +1055,10 @@ __device__ void leaf_fill(const Leaf& L, uint64_t* out) {
 
 // Persistent leaf loop: job i of the class's list goes to work-group
 // i mod G, whose job records are read kCacheLeaves at a time into LDS.
-// kPow2: the front list (sparse leaves over power-of-two ranges) with only
-// that leaf body compiled in, so that the hot path keeps its values in
-// registers; otherwise the back list with every other leaf body.
+// kPow2: the front list (sparse and with-replacement leaves over power-of-two
+// ranges) with only that leaf body compiled in, so that the hot path keeps
+// its values in registers; otherwise the back list with every other leaf
+// body.
 template <int B, bool kPow2>
 __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
                                           uint64_t* out, Control* ctl) {
@@ -1127,10 +1228,10 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
     kind = static_cast<uint64_t>(I.dense_ratio) * v.nv >= v.Nv ? kKindDense : kKindSparse;
   uint64_t pieces = 1;
   if (kind == kKindFill && v.nv > kFillPiece) pieces = (v.nv + kFillPiece - 1) / kFillPiece;
-  // sparse leaves over a power-of-two range fill the job array from the
-  // front, everything else from the back; the leaf kernel of the other class
-  // reports the two lists meeting
-  const bool front = kind == kKindSparse && (v.Nv & (v.Nv - 1)) == 0;
+  // sparse and with-replacement leaves over a power-of-two range fill the
+  // job array from the front, everything else from the back; the leaf
+  // kernel of the other class reports the two lists meeting
+  const bool front = (kind == kKindSparse || kind == kKindWr) && (v.Nv & (v.Nv - 1)) == 0;
   // one counter word at a uniform address, so that the compiler combines
   // the wave's increments into a single atomic
   const unsigned long long old =

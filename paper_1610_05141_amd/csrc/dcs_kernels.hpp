@@ -49,13 +49,14 @@ constexpr uint32_t kKindFill = 3;    // with replacement, N_v = 1: constant
 
 // Control block at the start of a workspace.
 struct Control {
-  // leaf jobs appended by the tree kernels: low 32 bits count the sparse
-  // leaves over power-of-two ranges (filled from the front of the job array),
+  // leaf jobs appended by the tree kernels: low 32 bits count the sparse and
+  // with-replacement leaves over power-of-two ranges (filled from the front
+  // of the job array),
   // high 32 bits all others (filled from the back); one 64-bit atomic
   // serves both
   unsigned long long leaf_counts;
   unsigned long long pad0;
-  unsigned long long chunk_ticket; // Bernoulli: next chunk to hand out
+  unsigned long long chunk_ticket; // FP64 Bernoulli: next chunk to hand out
   unsigned int error;              // latched error bits (kErr*)
   unsigned int pad;
   unsigned long long bern_count;   // Bernoulli: total hits (copied to the caller)
@@ -103,7 +104,8 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
                        uint32_t stack_depth, Control* ctl, hipStream_t stream);
 // Leaf kernel over one of the two job lists: pow2_list = the front list
-// (sparse leaves over power-of-two ranges), else the back list (all others).
+// (sparse and with-replacement leaves over power-of-two ranges), else the
+// back list (all others).
 hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream);
 // Dense leaves of the back list whose range fits 16-bit positions, one wave

@@ -42,6 +42,10 @@ WOR_CASES = [
     # (work-group path) in one sample
     (1 << 17, 1 << 22, 23, 4096, 64),
     (3000, 3000 * 64, 24, 4096, 64),          # one dense leaf over more than 2^16
+    # half of all words void: fewer than n_v values among the first 4096
+    # words, so the leaf takes the general rounds from word 0
+    (3000, 2**31 + 1, 25, 4096, 16),
+    (1 << 18, 3 * 2**30 + 7, 26, 4096, 16),   # a third void at the root's leaves
 ]
 
 
@@ -124,6 +128,8 @@ WR_CASES = [
     (3000, 2**45 + 1, 9, 4096),
     (4000, 8, 12, 4096),             # one leaf, 8 values: buckets of ~500 equal keys
     (4095, 5, 13, 4096),
+    (3000, 2**31 + 1, 14, 4096),     # half of all words void: general rounds
+    (1 << 18, 10**9 + 7, 15, 4096),  # ranges that are not powers of two
 ]
 
 
