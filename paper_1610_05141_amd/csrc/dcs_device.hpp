@@ -264,12 +264,24 @@ __device__ __forceinline__ double lnfact_diff(uint64_t a, uint64_t b) {
 }
 
 // ---------------------------------------------------------------------------
-// Exact floor(x*y/z) for x*y < 2^128, z > 0: a double estimate corrected with
-// 128-bit integer comparisons.
+// Exact floor(x*y/z) for x, y, z < 2^53 and a quotient below 2^53 (the
+// splits' modes): the FP64 quotient is within 2 of it, and 128-bit products
+// correct it (a 128-bit integer division would run bit by bit).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t floor_muldiv(uint64_t x, uint64_t y, uint64_t z) {
-  const unsigned __int128 prod = static_cast<unsigned __int128>(x) * y;
-  return static_cast<uint64_t>(prod / z);
+  const unsigned __int128 p = static_cast<unsigned __int128>(x) * y;
+  const double e = (static_cast<double>(x) * static_cast<double>(y)) / static_cast<double>(z);
+  uint64_t q = e < 0x1p63 ? static_cast<uint64_t>(e) : (1ull << 63);
+  unsigned __int128 qz = static_cast<unsigned __int128>(q) * z;
+  while (qz > p) {
+    --q;
+    qz -= z;
+  }
+  while (p - qz >= z) {
+    ++q;
+    qz += z;
+  }
+  return q;
 }
 
 // ---------------------------------------------------------------------------
@@ -288,7 +300,7 @@ __device__ __forceinline__ bool rou_accept(double u, double T, bool* reject) {
 }
 
 // Hypergeometric core for 1 <= n, M <= N/2.
-__device__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, Draws64& d) {
+__device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, Draws64& d) {
   const uint64_t q = n < M ? n : M;
   const uint64_t big = n < M ? M : n;
   if (q <= kInversionMax) {
@@ -337,7 +349,7 @@ __device__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, Draws64& d) {
 
 // Hyp(n, M, N): successes among n draws without replacement from N items, M
 // of them successes; stream (seed, node, SPLIT, 0).
-__device__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t seed,
+__device__ __forceinline__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t seed,
                                    uint64_t node) {
   if (n == 0 || M == 0) return 0;
   if (M == N) return n;
@@ -354,7 +366,7 @@ __device__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t 
 }
 
 // Binomial core for 1 <= l <= Nv - l.
-__device__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t Nv, Draws64& d) {
+__device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t Nv, Draws64& d) {
   const uint64_t r = Nv - l;
   if (n <= kInversionMax) {
     const double qv = static_cast<double>(r) / static_cast<double>(Nv);
@@ -401,7 +413,7 @@ __device__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t Nv, Draws64& d) 
 }
 
 // Bin(n, l/Nv) from stream (seed, node, WRSPLIT, 0).
-__device__ uint64_t binomial(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed, uint64_t node) {
+__device__ __forceinline__ uint64_t binomial(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed, uint64_t node) {
   if (n == 0 || l == 0) return 0;
   if (l == Nv) return n;
   Draws64 d{make_stream(seed, node, kWrSplit, 0), 0};
