@@ -1023,24 +1023,36 @@ __device__ void leaf_dense_wave(const Leaf& L, uint64_t* out, uint16_t* list, ui
     uint32_t done = 0;
     const uint64_t b1 = L.lo + 1;
     constexpr uint32_t kSpare = (kWaveListChunks - 1) * kWaveChunk;  // recomputed chunks
-    for (uint32_t k0 = 0; k0 < cnt; k0 += 64u) {
-      const uint32_t k = k0 + lane;
-      uint32_t pos = k;
-      if (!full) {
-        const uint32_t c = k0 / kWaveChunk;
-        if (c >= kWaveListChunks && (k0 % kWaveChunk) == 0) {
-          uint32_t q[4];
-          skip_chunk(st, c, lane, cg, bases[c], q);
-          put_chunk(list + kSpare + 4u * lane, q);
-        }
-        const uint32_t slot = c < kWaveListChunks ? k : kSpare + (k - c * kWaveChunk);
-        if (k < cnt) pos = list[slot];
+    // One chunk per step: lane l takes hits k0 + 64s + l (s < 4), so the
+    // chunk's LDS reads issue together.
+    for (uint32_t k0 = 0; k0 < cnt; k0 += kWaveChunk) {
+      const uint32_t c = k0 / kWaveChunk;
+      uint32_t sbase = k0;  // list index of hit k0
+      if (!full && c >= kWaveListChunks) {
+        uint32_t q[4];
+        skip_chunk(st, c, lane, cg, bases[c], q);
+        put_chunk(list + kSpare + 4u * lane, q);
+        sbase = kSpare;
       }
-      const bool kept = k < cnt && !((mask[k >> 5] >> (k & 31u)) & 1u);
-      const unsigned long long K = __ballot(kept);
-      const uint32_t at = done + lane_rank(K);
-      if (kept && at < nv) store_out(o0 + at, b1 + pos);
-      done += static_cast<uint32_t>(__popcll(K));
+      uint32_t pos[4], rm[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t k = k0 + 64u * t + lane;
+        // every index stays inside the list and the mask; values past the
+        // last hit are read but never stored
+        pos[t] = full ? k : static_cast<uint32_t>(list[sbase + 64u * t + lane]);
+        const uint32_t w = k >> 5;
+        rm[t] = mask[w < kWaveMaskWords ? w : kWaveMaskWords - 1];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t k = k0 + 64u * t + lane;
+        const bool kept = k < cnt && !((rm[t] >> (k & 31u)) & 1u);
+        const unsigned long long K = __ballot(kept);
+        const uint32_t at = done + lane_rank(K);
+        if (kept && at < nv) store_out(o0 + at, b1 + pos[t]);
+        done += static_cast<uint32_t>(__popcll(K));
+      }
     }
     break;
   }
@@ -1620,19 +1632,33 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
       ctl->bern_count = first + cnt;
     }
     uint32_t qb = 0;
-    for (uint32_t k0 = 0; k0 < cnt; k0 += 64u) {
+    // one 256-draw group per step: lane l takes hits k0 + 64s + l (s < 4)
+    for (uint32_t k0 = 0; k0 < cnt; k0 += kBernWaveGroup) {
       const uint32_t c = k0 / kBernWaveGroup;
-      if (c >= kBernWaveGroups && (k0 % kBernWaveGroup) == 0) {
+      uint32_t sbase = k0;  // list index of hit k0
+      if (c >= kBernWaveGroups) {
         uint32_t inc[4];
         bern_group(st, c, lane, c32, inc);
         put_incs(list + kSpare + 4u * lane, inc);
+        sbase = kSpare;
       }
-      const uint32_t k = k0 + lane;
-      const uint32_t slot = c < kBernWaveGroups ? k : kSpare + (k - c * kBernWaveGroup);
-      const uint32_t inc = k < cnt ? static_cast<uint32_t>(list[slot]) : 0u;
-      const uint32_t incl = wave_scan_incl(inc);
-      if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + incl);
-      qb += __builtin_amdgcn_readlane(incl, 63);
+      uint32_t inc[4], incl[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t k = k0 + 64u * t + lane;
+        // list indices stay inside the list; increments past the last hit
+        // are dropped here
+        const uint32_t v = list[sbase + 64u * t + lane];
+        inc[t] = k < cnt ? v : 0u;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) incl[t] = wave_scan_incl(inc[t]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t k = k0 + 64u * t + lane;
+        if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + incl[t]);
+        qb += __builtin_amdgcn_readlane(incl[t], 63);
+      }
     }
   }
 }
