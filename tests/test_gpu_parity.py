@@ -46,6 +46,10 @@ WOR_CASES = [
     # words, so the leaf takes the general rounds from word 0
     (3000, 2**31 + 1, 25, 4096, 16),
     (1 << 18, 3 * 2**30 + 7, 26, 4096, 16),   # a third void at the root's leaves
+    # density 0.49 with dense ratio 2: ~490 repeats in the first round (a full
+    # re-sort round), then rounds of at most 256 new values merged in
+    (2000, 4100, 27, 4096, 2),
+    (3900, 7900, 28, 4096, 2),
 ]
 
 
