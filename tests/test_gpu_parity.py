@@ -200,6 +200,37 @@ def test_bernoulli_small_n0_matches_oracle(ref, p, N, seed, n0):
     assert np.array_equal(got, want), first_mismatch(got, want)
 
 
+@pytest.mark.parametrize("p,N,seed", [(0.01, 1 << 24, 31), (0.5, 1 << 20, 32)])
+def test_bernoulli_output_one_element_off_alignment(ref, p, N, seed):
+    """Output that starts 8 bytes past a 16-byte boundary: the paired stores
+    must fall back to single ones."""
+    import torch
+    m = dcs()
+    announce(f"bernoulli unaligned p={p} N={N}")
+    want = ref.bernoulli(p, N, seed)
+    cap = want.size + 64
+    buf = torch.zeros(cap + 1, dtype=torch.int64, device="cuda")
+    out = buf[1:]
+    assert out.data_ptr() % 16 == 8
+    _, cnt = m.sample_bernoulli(p, N, seed, out=out, capacity=cap)
+    m.synchronize()
+    assert int(cnt.item()) == want.size
+    assert int(buf[0].item()) == 0
+    assert np.array_equal(to_np_u64(out[:want.size]), want)
+
+
+def test_wor_output_one_element_off_alignment(ref):
+    import torch
+    m = dcs()
+    n, N, seed = 300000, 10**9 + 7, 33
+    announce("wor unaligned")
+    buf = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    m.sample(n, N, seed, out=buf[1:])
+    m.synchronize()
+    assert int(buf[0].item()) == 0
+    assert np.array_equal(to_np_u64(buf[1:]), ref.sample(n, N, seed))
+
+
 def test_bernoulli_capacity_overflow_keeps_prefix(ref):
     import torch
     m = dcs()
