@@ -250,6 +250,10 @@ const char* dcs_status_string(int32_t status);
  * kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
+/* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind
+ * k; all kinds by default), so that a timed loop records events only around
+ * the kernels it reports; always DCS_OK. */
+int32_t dcs_profile_kinds(uint32_t mask);
 
 /*
  * Diagnostics: the device primitives applied elementwise to device arrays,

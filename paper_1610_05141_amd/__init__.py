@@ -15,7 +15,7 @@ from dataclasses import dataclass
 __all__ = [
     "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
-    "profile_read", "debug_primitive", "tune_set", "tune_get", "tune_reset",
+    "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
 
@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = (
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
-    "dcs_profile_read", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
+    "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
     "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset",
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "dcs_status_string": (ctypes.c_char_p, [i32]),
             "dcs_profile_enable": (i32, [i32]),
             "dcs_profile_read": (i32, [i32, ctypes.POINTER(dbl), ctypes.POINTER(u64)]),
+            "dcs_profile_kinds": (i32, [u32]),
             "dcs_debug_primitive": (i32, [i32, vp, vp, vp, u64, u64, u64, u64, u64, vp]),
             "dcs_server_create": (i32, [u64, u32, u32, i32, ctypes.POINTER(vp)]),
             "dcs_server_submit": (i32, [vp, ctypes.POINTER(_Request), dbl, ctypes.POINTER(u64)]),
@@ -278,6 +279,12 @@ def tune_get(variant: int, log2_n: int):
 
 def tune_reset() -> None:
     _check(lib().dcs_tune_reset(), "dcs_tune_reset")
+
+
+def profile_kinds(kinds=None):
+    """Time only the given kernel kinds (an iterable of ints; None = all)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << int(k) for k in kinds)
+    _check(lib().dcs_profile_kinds(mask), "dcs_profile_kinds")
 
 
 def profile_read(kind: int):

@@ -182,7 +182,8 @@ double host_log1p_series(double x) {
 // ---- device context -------------------------------------------------------
 struct Timing {
   int kind;
-  hipEvent_t a, b;
+  int dev;
+  hipEvent_t a, b;  // a == nullptr: this launch is not timed
 };
 
 
@@ -191,6 +192,28 @@ std::vector<DeviceCtx> g_dev;
 std::set<void*> g_ctl_used;  // control blocks to check at synchronize
 bool g_profile = false;
 std::vector<Timing> g_timings;
+uint32_t g_prof_mask = ~0u;                        // kinds that are timed
+std::vector<std::vector<hipEvent_t>> g_event_pool;  // per device, reused events
+
+hipEvent_t pooled_event(int dev) {
+  if (static_cast<int>(g_event_pool.size()) <= dev) g_event_pool.resize(dev + 1);
+  auto& pool = g_event_pool[dev];
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void release_timings() {
+  for (Timing& t : g_timings) {
+    g_event_pool[t.dev].push_back(t.a);
+    g_event_pool[t.dev].push_back(t.b);
+  }
+  g_timings.clear();
+}
 // kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
 // 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
 // the rest, 6 one-wave dense leaf kernel
@@ -259,15 +282,23 @@ int32_t own_workspace(DeviceCtx* c, size_t bytes, void** ws) {
 }
 
 void timing_begin(int kind, hipStream_t s, Timing* t) {
-  if (!g_profile) return;
+  t->a = t->b = nullptr;
+  if (!g_profile || !((g_prof_mask >> kind) & 1u)) return;
+  if (hipGetDevice(&t->dev) != hipSuccess) return;
   t->kind = kind;
-  (void)hipEventCreate(&t->a);
-  (void)hipEventCreate(&t->b);
+  t->a = pooled_event(t->dev);
+  t->b = pooled_event(t->dev);
+  if (t->a == nullptr || t->b == nullptr) {
+    if (t->a) g_event_pool[t->dev].push_back(t->a);
+    if (t->b) g_event_pool[t->dev].push_back(t->b);
+    t->a = t->b = nullptr;
+    return;
+  }
   (void)hipEventRecord(t->a, s);
 }
 
 void timing_end(hipStream_t s, Timing* t) {
-  if (!g_profile) return;
+  if (t->a == nullptr) return;
   (void)hipEventRecord(t->b, s);
   g_timings.push_back(*t);
 }
@@ -656,10 +687,8 @@ int32_t dcs_synchronize(void* stream) {
         g_prof_ms[t.kind] += ms;
         g_prof_n[t.kind] += 1;
       }
-      (void)hipEventDestroy(t.a);
-      (void)hipEventDestroy(t.b);
     }
-    g_timings.clear();
+    release_timings();
   }
   return any ? DCS_EDEVICE : DCS_OK;
 }
@@ -706,16 +735,18 @@ int32_t dcs_tune_reset(void) {
 
 int32_t dcs_profile_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_mu);
-  for (Timing& t : g_timings) {
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
-  }
-  g_timings.clear();
+  release_timings();
   for (int i = 0; i < kProfKinds; ++i) {
     g_prof_ms[i] = 0;
     g_prof_n[i] = 0;
   }
   g_profile = enable != 0;
+  return DCS_OK;
+}
+
+int32_t dcs_profile_kinds(uint32_t mask) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_mask = mask;
   return DCS_OK;
 }
 
