@@ -1549,13 +1549,14 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
 
 // Single-precision Bernoulli chunks (p >= 2^-10), one wave per chunk and no
 // barrier: chunk j's hits are its draws up to the one that passes the chunk
-// end (Sec. 4.7's skips); the wave keeps their increments, which are below
-// 22.2/p + 1 < 2^16, as 16-bit values (the first kBernWaveList of them;
-// later 256-draw groups are recomputed when written), publishes its count for
-// the look-back, and writes the positions as a running sum, consecutive lanes
-// on consecutive outputs.
+// end (Sec. 4.7's skips).  The wave keeps each 256-draw group of the first
+// kBernWaveGroups as 16-bit values: the positions relative to the group's
+// start when the group advances less than 2^16, else the increments (below
+// 22.2/p + 1 < 2^16), rebuilt by wave scans when written; later groups are
+// recomputed when written.  It publishes its count for the look-back and
+// writes consecutive lanes on consecutive outputs.
 constexpr uint32_t kBernWaveGroup = 256;                     // draws per group
-constexpr uint32_t kBernWaveGroups = 16;                     // groups kept in LDS
+constexpr uint32_t kBernWaveGroups = 15;                     // groups kept in LDS
 constexpr uint32_t kBernWaveList = kBernWaveGroup * kBernWaveGroups;
 
 // Increments of draw group c (lane l: draws 256c + 4l + j) into dst, and
@@ -1586,6 +1587,7 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
                                                   Control* ctl, unsigned long long* tickets,
                                                   uint32_t n_cls) {
   __shared__ __align__(16) uint16_t list[kBernWaveList];
+  __shared__ uint32_t gbase[kBernWaveGroups + 1];  // position before group c (c <= 15)
   const uint32_t lane = lane_tid();
   constexpr uint32_t kSpare = (kBernWaveGroups - 1) * kBernWaveGroup;  // recomputed groups
   // Chunks are handed out by n_cls counters, 256 bytes apart: this wave's
@@ -1607,23 +1609,31 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
     const Stream st = make_stream(seed, j, kBChunk, 0);
     // hits: the draws whose running position stays within the chunk
     uint32_t q_base = 0, cnt = 0;
+    uint32_t rel_groups = 0;  // bit c: group c holds relative positions
     for (uint32_t c = 0;; ++c) {
       uint32_t inc[4];
       const uint32_t sum = bern_group(st, c, lane, c32, inc);
       const uint32_t incl = wave_scan_incl(sum);
-      uint32_t q = q_base + incl - sum;
-      uint32_t in = 0;
+      const uint32_t adv = __builtin_amdgcn_readlane(incl, 63);
+      uint32_t rel[4];
+      uint32_t r = incl - sum, in = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        q += inc[k];
-        in += q <= len ? 1u : 0u;
+        r += inc[k];
+        rel[k] = r;
+        in += q_base + r <= len ? 1u : 0u;
       }
-      if (c < kBernWaveGroups) put_incs(list + c * kBernWaveGroup + 4u * lane, inc);
+      if (c <= kBernWaveGroups && lane == 0) gbase[c] = q_base;
+      if (c < kBernWaveGroups) {
+        const bool as_rel = adv < 0x10000u;
+        put_incs(list + c * kBernWaveGroup + 4u * lane, as_rel ? rel : inc);
+        rel_groups |= (as_rel ? 1u : 0u) << c;
+      }
       const unsigned long long whole = __ballot(in == 4u);
       const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
       const uint32_t got = nw == 64u ? kBernWaveGroup : 4u * nw + __builtin_amdgcn_readlane(in, nw);
       cnt += got;
-      q_base += __builtin_amdgcn_readlane(incl, 63);
+      q_base += adv;
       if (got < kBernWaveGroup) break;
     }
     const uint64_t first = bern_lookback(status, j, cnt, ctl);
@@ -1631,33 +1641,51 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
       *count_dev = first + cnt;
       ctl->bern_count = first + cnt;
     }
-    uint32_t qb = 0;
-    // one 256-draw group per step: lane l takes hits k0 + 64s + l (s < 4)
+    // one 256-draw group per step: lane l takes hits k0 + 64s + l (s < 4);
+    // qb: position before the group
+    uint32_t qrun = 0;  // position before the next recomputed group
     for (uint32_t k0 = 0; k0 < cnt; k0 += kBernWaveGroup) {
       const uint32_t c = k0 / kBernWaveGroup;
       uint32_t sbase = k0;  // list index of hit k0
-      if (c >= kBernWaveGroups) {
+      bool as_rel = false;
+      uint32_t qb;
+      if (c < kBernWaveGroups) {
+        qb = gbase[c];
+        as_rel = (rel_groups >> c) & 1u;
+      } else {
+        if (c == kBernWaveGroups) qrun = gbase[c];
         uint32_t inc[4];
-        bern_group(st, c, lane, c32, inc);
+        const uint32_t sum = bern_group(st, c, lane, c32, inc);
         put_incs(list + kSpare + 4u * lane, inc);
+        qb = qrun;
+        qrun += __builtin_amdgcn_readlane(wave_scan_incl(sum), 63);
         sbase = kSpare;
       }
-      uint32_t inc[4], incl[4];
+      uint32_t v[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const uint32_t k = k0 + 64u * t + lane;
-        // list indices stay inside the list; increments past the last hit
-        // are dropped here
-        const uint32_t v = list[sbase + 64u * t + lane];
-        inc[t] = k < cnt ? v : 0u;
+        // list indices stay inside the list; values past the last hit are
+        // dropped here
+        const uint32_t x = list[sbase + 64u * t + lane];
+        v[t] = k < cnt ? x : 0u;
       }
+      if (as_rel) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) incl[t] = wave_scan_incl(inc[t]);
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t k = k0 + 64u * t + lane;
+          if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + v[t]);
+        }
+      } else {
+        uint32_t incl[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const uint32_t k = k0 + 64u * t + lane;
-        if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + incl[t]);
-        qb += __builtin_amdgcn_readlane(incl[t], 63);
+        for (int t = 0; t < 4; ++t) incl[t] = wave_scan_incl(v[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t k = k0 + 64u * t + lane;
+          if (k < cnt && first + k < capacity) store_out(out + first + k, base + qb + incl[t]);
+          qb += __builtin_amdgcn_readlane(incl[t], 63);
+        }
       }
     }
   }
