@@ -10,6 +10,8 @@ import sys
 import numpy as np
 import pytest
 
+from tests.gpu_util import announce, dcs
+
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -79,3 +81,27 @@ def test_tuning_table_geometry_invariance(ref):
     finally:
         for (variant, k), (cb, w) in saved.items():
             m.tune_set(variant, k, cb, w)
+
+
+def test_profile_kinds_times_only_the_selected_kernels():
+    """dcs_profile_kinds: with only kind 4 selected, a sample records launches
+    of the power-of-two leaf kernel and none of the tree or the other leaf
+    kernels; with every kind selected, all of them."""
+    m = dcs()
+    announce("profile kinds")
+    n, N = 1 << 18, 1 << 36
+    try:
+        m.profile_kinds([4])
+        m.profile_enable(True)
+        m.sample(n, N, 5)
+        m.synchronize()
+        assert m.profile_read(4)[1] == 1
+        assert all(m.profile_read(k)[1] == 0 for k in (0, 1, 2, 5, 6))
+        m.profile_kinds(None)
+        m.profile_enable(True)
+        m.sample(n, N, 5)
+        m.synchronize()
+        assert all(m.profile_read(k)[1] == 1 for k in (0, 1, 2, 4, 5, 6))
+    finally:
+        m.profile_kinds(None)
+        m.profile_enable(False)
