@@ -299,7 +299,42 @@ __device__ __forceinline__ bool rou_accept(double u, double T, bool* reject) {
   return 2.0 * log64(u) <= T;
 }
 
+// The ratio-of-uniforms loop: attempt a takes draws 2a (U) and 2a+1 (V),
+// i.e. Philox block a, and the deviate is the first accepted attempt.
+// kWave: the 64 lanes of a wave, all sampling the same deviate, try
+// attempts 64r + lane of round r and take the lowest accepted one (the same
+// deviate, found in one round instead of one attempt after another).
+template <bool kWave, class Attempt>
+__device__ __forceinline__ uint64_t rou_first_accepted(Draws64& d, Attempt attempt) {
+  if constexpr (kWave) {
+    uint32_t lane = threadIdx.x & 63u;
+    asm volatile("" : "+v"(lane));
+    for (uint32_t round = 0;; ++round) {
+      const uint4 b = philox_block(d.s, round * 64u + lane);
+      const double u = unit_open0(static_cast<uint64_t>(b.x) | (static_cast<uint64_t>(b.y) << 32));
+      const double v = unit_closed0(static_cast<uint64_t>(b.z) | (static_cast<uint64_t>(b.w) << 32));
+      uint64_t k = 0;
+      const bool ok = attempt(u, v, &k);
+      const unsigned long long m = __ballot(ok);
+      if (m != 0) {
+        const uint32_t f = static_cast<uint32_t>(__ffsll(static_cast<long long>(m)) - 1);
+        const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(k), f);
+        const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(k >> 32), f);
+        return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+      }
+    }
+  } else {
+    for (;;) {
+      const double u = unit_open0(d.next());
+      const double v = unit_closed0(d.next());
+      uint64_t k = 0;
+      if (attempt(u, v, &k)) return k;
+    }
+  }
+}
+
 // Hypergeometric core for 1 <= n, M <= N/2.
+template <bool kWave>
 __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, Draws64& d) {
   const uint64_t q = n < M ? n : M;
   const uint64_t big = n < M ? M : n;
@@ -332,23 +367,24 @@ __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N,
   if (kcap < static_cast<double>(kmax)) kmax = static_cast<uint64_t>(kcap);
   const double kmax_d = static_cast<double>(kmax);
   const uint64_t rest = N - M - n;
-  for (;;) {
-    const double u = unit_open0(d.next());
-    const double v = unit_closed0(d.next());
+  return rou_first_accepted<kWave>(d, [&](double u, double v, uint64_t* out) {
     const double x = a + (s * (v - 0.5)) / u;
-    if (x < 0.0 || x >= kmax_d) continue;
+    if (x < 0.0 || x >= kmax_d) return false;
     const uint64_t k = static_cast<uint64_t>(floor(x));
     double T = lnfact_diff(mode, k);
     T = T + lnfact_diff(M - mode, M - k);
     T = T + lnfact_diff(n - mode, n - k);
     T = T + lnfact_diff(rest + mode, rest + k);
     bool rej;
-    if (rou_accept(u, T, &rej)) return k;
-  }
+    *out = k;
+    return rou_accept(u, T, &rej);
+  });
 }
 
 // Hyp(n, M, N): successes among n draws without replacement from N items, M
-// of them successes; stream (seed, node, SPLIT, 0).
+// of them successes; stream (seed, node, SPLIT, 0).  kWave: called by all 64
+// lanes of a wave with the same arguments.
+template <bool kWave = false>
 __device__ __forceinline__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t seed,
                                    uint64_t node) {
   if (n == 0 || M == 0) return 0;
@@ -359,13 +395,14 @@ __device__ __forceinline__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint6
   const uint64_t n1 = flip_n ? N - n : n;
   const bool flip_m = M > N - M;
   const uint64_t M1 = flip_m ? N - M : M;
-  uint64_t k = hyp_core(n1, M1, N, d);
+  uint64_t k = hyp_core<kWave>(n1, M1, N, d);
   if (flip_m) k = n1 - k;
   if (flip_n) k = M - k;
   return k;
 }
 
 // Binomial core for 1 <= l <= Nv - l.
+template <bool kWave>
 __device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t Nv, Draws64& d) {
   const uint64_t r = Nv - l;
   if (n <= kInversionMax) {
@@ -398,27 +435,28 @@ __device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t 
   const double lodds = log1p64(
       static_cast<double>(static_cast<int64_t>(2 * l) - static_cast<int64_t>(Nv)) /
       static_cast<double>(r));
-  for (;;) {
-    const double u = unit_open0(d.next());
-    const double v = unit_closed0(d.next());
+  return rou_first_accepted<kWave>(d, [&](double u, double v, uint64_t* out) {
     const double x = a + (s * (v - 0.5)) / u;
-    if (x < 0.0 || x >= kmax_d) continue;
+    if (x < 0.0 || x >= kmax_d) return false;
     const uint64_t k = static_cast<uint64_t>(floor(x));
     double T = static_cast<double>(static_cast<int64_t>(k) - static_cast<int64_t>(mode)) * lodds;
     T = T + lnfact_diff(mode, k);
     T = T + lnfact_diff(n - mode, n - k);
     bool rej;
-    if (rou_accept(u, T, &rej)) return k;
-  }
+    *out = k;
+    return rou_accept(u, T, &rej);
+  });
 }
 
-// Bin(n, l/Nv) from stream (seed, node, WRSPLIT, 0).
+// Bin(n, l/Nv) from stream (seed, node, WRSPLIT, 0).  kWave: called by all
+// 64 lanes of a wave with the same arguments.
+template <bool kWave = false>
 __device__ __forceinline__ uint64_t binomial(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed, uint64_t node) {
   if (n == 0 || l == 0) return 0;
   if (l == Nv) return n;
   Draws64 d{make_stream(seed, node, kWrSplit, 0), 0};
-  if (l > Nv - l) return n - binom_core(n, Nv - l, Nv, d);
-  return binom_core(n, l, Nv, d);
+  if (l > Nv - l) return n - binom_core<kWave>(n, Nv - l, Nv, d);
+  return binom_core<kWave>(n, l, Nv, d);
 }
 
 __host__ __device__ __forceinline__ uint64_t isqrt64(uint64_t x) {

@@ -1225,10 +1225,11 @@ __device__ __forceinline__ bool is_leaf(const Node& v, const Instance& I) {
   return v.nv < I.n0 && v.Nv <= kLeafMaxRange;
 }
 
+template <bool kWave = false>
 __device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I) {
   const uint64_t l = v.Nv >> 1;
-  return I.variant == 1 ? binomial(v.nv, l, v.Nv, I.seed, v.id)
-                        : hypergeometric(v.nv, l, v.Nv, I.seed, v.id);
+  return I.variant == 1 ? binomial<kWave>(v.nv, l, v.Nv, I.seed, v.id)
+                        : hypergeometric<kWave>(v.nv, l, v.Nv, I.seed, v.id);
 }
 
 __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* leaves, uint64_t cap,
@@ -1280,8 +1281,10 @@ __device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t
 
 // Walk levels [d0, d1) of Algorithm P from node v along the bits of g (bit
 // d1-1-d chooses the child at depth d).  Returns false when the walk ended
-// early at a leaf or an empty node (the leaf is emitted by the thread whose
-// remaining bits are zero).
+// early at a leaf or an empty node (the leaf is emitted by the path whose
+// remaining bits are zero).  kWave: the 64 lanes of a wave walk one path
+// together (lane 0 emits) and share each split's rejection attempts.
+template <bool kWave = false>
 __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uint64_t g,
                                           const Instance& I, Leaf* leaves, uint64_t leaf_cap,
                                           Control* ctl) {
@@ -1289,10 +1292,11 @@ __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uin
     if (v.nv == 0) return false;
     if (is_leaf(v, I)) {
       const uint32_t below = d1 - d;
-      if ((g & ((1ull << below) - 1)) == 0) emit(v, I, leaves, leaf_cap, ctl);
+      if ((g & ((1ull << below) - 1)) == 0 && (!kWave || (threadIdx.x & 63u) == 0))
+        emit(v, I, leaves, leaf_cap, ctl);
       return false;
     }
-    const uint64_t L = split_left(v, I);
+    const uint64_t L = split_left<kWave>(v, I);
     const uint64_t l = v.Nv >> 1;
     if ((g >> (d1 - 1 - d)) & 1) {
       v = Node{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
@@ -1303,17 +1307,20 @@ __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uin
   return true;
 }
 
+// One wave per top path (top_threads paths, 64 lanes each): the splits
+// above the frontier form the longest chain of the tree, and a wave finds
+// each split's accepted attempt in one round of 64.
 __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ inst,
                                                   uint32_t n_inst, uint64_t top_threads,
                                                   Node* frontier, Leaf* leaves, uint64_t leaf_cap,
                                                   Control* ctl) {
-  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= top_threads) return;
+  const uint64_t t = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (t >= top_threads) return;  // whole waves
   const Instance I = inst[find_instance(inst, n_inst, t, true)];
   const uint64_t g = t - I.top_base;
   Node v{1, 0, I.N, I.n, 0};
-  if (!walk_path(v, 0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
-  frontier[t] = v;
+  if (!walk_path<true>(v, 0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
+  if ((threadIdx.x & 63u) == 0) frontier[t] = v;
 }
 
 __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
@@ -1806,7 +1813,7 @@ hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_t
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
                            hipStream_t stream) {
   if (top_threads == 0) return hipSuccess;
-  const uint64_t blocks = (top_threads + 255) / 256;
+  const uint64_t blocks = (top_threads * 64 + 255) / 256;  // one wave per path
   hipLaunchKernelGGL(k_tree_top, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
                      n_inst, top_threads, frontier, leaves, leaf_cap, ctl);
   return hipGetLastError();
