@@ -106,6 +106,36 @@ int32_t dcs_sample_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t* out_
 int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_params* params,
                                 uint64_t* out_dev, uint64_t capacity, uint64_t* count_dev,
                                 void* workspace, size_t ws_bytes, void* stream);
+/*
+ * dcs_sample_part -- one part of the sample that dcs_sample (variant 0) or
+ * dcs_sample_replacement (variant 1) returns for (n, N, seed, params), so
+ * that a sample can be produced piece by piece in sorted order with bounded
+ * memory (Sec. 4.1: online sampling by splitting off subranges; Sec. 3.2:
+ * every node's decisions depend only on its identity, so any part can be
+ * computed on its own).  The parts are the 2^depth nodes of the recursion
+ * tree at depth `depth` (node `index`, 0-based from the left, covers a
+ * contiguous range of 1..N); a leaf that ends a path above that depth
+ * belongs, whole, to the leftmost part below it, and the other parts below
+ * it are empty.  Part 0, 1, ..., 2^depth - 1 concatenated is the full sample.
+ *   out_dev:        capacity uint64 slots, device memory; the part's values,
+ *                   ascending, are written from out_dev[0] if they fit.
+ *   count_rank_dev: two uint64 in device memory: [0] the number of values in
+ *                   the part, [1] its rank (values of the sample in the parts
+ *                   before it, i.e. where the part starts in the full sample).
+ * The state needed to continue a piecewise traversal is (depth, index).  If
+ * the count exceeds `capacity`, nothing is written to out_dev (the count is
+ * only known on the device: compare count_rank_dev[0] with capacity after
+ * synchronizing; re-running with a larger buffer gives the same values).
+ * Errors: DCS_EINVAL for a bad variant, the argument errors of the full
+ * call, depth > DCS_MAX_PART_DEPTH, index >= 2^depth, count_rank_dev NULL,
+ * or out_dev NULL with capacity > 0.  Uses the library's workspace.
+ */
+#define DCS_MAX_PART_DEPTH 45
+int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
+                        const dcs_params* params, uint32_t depth, uint64_t index,
+                        uint64_t* out_dev, uint64_t capacity, uint64_t* count_rank_dev,
+                        void* stream);
+
 /* A capacity that the Bernoulli count exceeds with negligible probability:
  * Np + 10 sqrt(Np(1-p)) + 64. */
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N);

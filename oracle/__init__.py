@@ -61,6 +61,8 @@ def configure(L: ctypes.CDLL) -> ctypes.CDLL:
             "dcs_ref_sample_window": (i32, [u64, u64, u64, u32, u32, u64, u64, p64]),
             "dcs_ref_replacement": (i32, [u64, u64, u64, u32, p64]),
             "dcs_ref_replacement_window": (i32, [u64, u64, u64, u32, u64, u64, p64]),
+            "dcs_ref_part": (i32, [i32, u64, u64, u64, u32, u32, u32, u64, p64, u64, p64,
+                                   p64]),
             "dcs_ref_bernoulli": (i32, [dbl, u64, u64, u32, p64, u64, p64]),
             "dcs_ref_bernoulli_chunks": (i32, [dbl, u64, u64, u32, u64, u64, p64, u64, p64]),
             "dcs_ref_bernoulli_chunk_len": (u64, [dbl, u32]),
@@ -133,6 +135,25 @@ def replacement_window(n: int, N: int, seed: int, start: int, count: int,
     _check(lib().dcs_ref_replacement_window(n, N, seed, n0, start, count, _p64(out)),
            "replacement_window")
     return out
+
+
+def part(variant: int, n: int, N: int, seed: int, depth: int, index: int,
+         n0: int = DEFAULT_N0, dense_ratio: int = DEFAULT_DENSE_RATIO,
+         capacity: int | None = None) -> tuple:
+    """Part `index` of the depth-`depth` cut of ``sample`` (variant 0) or
+    ``replacement`` (variant 1), Sec. 4.1 online sampling: returns
+    (values, count, rank); values is None when count exceeds capacity."""
+    cap = n if capacity is None else capacity
+    out = np.empty(max(cap, 1), dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rank = np.zeros(1, dtype=np.uint64)
+    rc = lib().dcs_ref_part(variant, n, N, seed, n0, dense_ratio, depth, index, _p64(out), cap,
+                            _p64(cnt), _p64(rank))
+    count, r = int(cnt[0]), int(rank[0])
+    if rc == 4:  # overflow: the part does not fit
+        return None, count, r
+    _check(rc, "part")
+    return out[:count].copy(), count, r
 
 
 def bernoulli(p: float, N: int, seed: int, n0: int = DEFAULT_N0,

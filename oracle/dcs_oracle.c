@@ -724,6 +724,66 @@ EXPORT int dcs_ref_replacement(uint64_t n, uint64_t N, uint64_t seed, uint32_t n
   return dcs_ref_replacement_window(n, N, seed, n0, 0, n, out);
 }
 
+/* Online sampling in parts (Sec. 4.1: the sorted sample is produced piece
+ * by piece, each piece a subrange split off by the recursion).  The parts
+ * at depth d are the 2^d nodes of the tree d levels below the root, from
+ * left to right; node `index` is reached by taking, at level i, the right
+ * child iff bit d-1-i of index is set.  A path that meets a leaf (or an
+ * empty node) above depth d stops there: the leaf's values form the part
+ * whose remaining index bits are all zero, and the other parts below it
+ * are empty.  *count is the part's size, *rank the number of values of the
+ * full sample in earlier parts; the values are written to out[0..count)
+ * when count <= capacity (REF_EOVERFLOW and nothing written otherwise). */
+EXPORT int dcs_ref_part(int variant, uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
+                        uint32_t dense_ratio, uint32_t depth, uint64_t index, uint64_t *out,
+                        uint64_t capacity, uint64_t *count, uint64_t *rank) {
+  if (count == NULL || rank == NULL) return REF_EINVAL;
+  *count = 0;
+  *rank = 0;
+  if (variant != 0 && variant != 1) return REF_EINVAL;
+  if (check_params(n0, dense_ratio) != REF_OK || N > REF_MAX_N) return REF_EINVAL;
+  if (variant == 0 && n > N) return REF_EINVAL;
+  if (variant == 1 && N == 0 && n > 0) return REF_EINVAL;
+  if (depth > 45 || index >= (1ULL << depth)) return REF_EINVAL;
+  ctx_t c = {seed, n0, dense_ratio};
+  uint64_t id = 1, lo = 0, Nv = N, nv = n, off = 0;
+  for (uint32_t level = 0; level < depth; ++level) {
+    int leaf = variant == 1 ? (Nv == 1 || (nv < n0 && Nv <= REF_LEAF_MAX_RANGE))
+                            : (nv < n0 && Nv <= REF_LEAF_MAX_RANGE);
+    if (nv == 0) break; /* empty node: every part below it is empty */
+    if (leaf) {
+      uint64_t rest = index & ((1ULL << (depth - level)) - 1);
+      if (rest != 0) { /* not the leftmost part below the leaf */
+        off += nv;
+        nv = 0;
+      }
+      break;
+    }
+    uint64_t l = Nv / 2;
+    uint64_t L = variant == 1 ? bin(nv, l, Nv, seed, id) : hyp(nv, l, Nv, seed, id);
+    if ((index >> (depth - 1 - level)) & 1) {
+      id = 2 * id + 1;
+      lo += l;
+      Nv -= l;
+      nv -= L;
+      off += L;
+    } else {
+      id = 2 * id;
+      Nv = l;
+      nv = L;
+    }
+  }
+  *count = nv;
+  *rank = off;
+  if (nv == 0) return REF_OK;
+  if (nv > capacity) return REF_EOVERFLOW;
+  if (out == NULL) return REF_EINVAL;
+  /* the node's subtree writes positions off .. off+nv of the full sample */
+  sink_t k = {out, off, off + nv};
+  return variant == 1 ? sample_wr(&c, id, lo, Nv, nv, off, &k)
+                      : sample_r(&c, id, lo, Nv, nv, off, &k);
+}
+
 /* Bernoulli sample of 1..N with probability p, chunks [jC, (j+1)C) sampled
  * independently with their own streams.  Writes the first `capacity` values
  * to out and the true count to *count.  Chunks [c0, c1) only when

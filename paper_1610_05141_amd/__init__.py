@@ -13,7 +13,8 @@ import os
 from dataclasses import dataclass
 
 __all__ = [
-    "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "synchronize",
+    "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "sample_part",
+    "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
@@ -28,6 +29,7 @@ DCS_OK, DCS_EINVAL, DCS_ENOMEM, DCS_EHIP, DCS_EOVERFLOW, DCS_EDEVICE, DCS_ENOTSU
 EXPORTED_SYMBOLS = (
     "dcs_sample", "dcs_sample_ex", "dcs_sample_replacement", "dcs_sample_replacement_ex",
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
+    "dcs_sample_part",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
     "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
@@ -91,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "dcs_sample_bernoulli_ex": (i32, [dbl, u64, u64, pp, vp, u64, vp, vp,
                                               ctypes.c_size_t, vp]),
             "dcs_bernoulli_capacity_hint": (u64, [dbl, u64]),
+            "dcs_sample_part": (i32, [i32, u64, u64, u64, pp, u32, u64, vp, u64, vp, vp]),
             "dcs_workspace_size": (i32, [i32, u64, u64, dbl, pp, ctypes.POINTER(ctypes.c_size_t)]),
             "dcs_batch_create": (i32, [ctypes.POINTER(_Instance), u32, ctypes.POINTER(vp),
                                        ctypes.POINTER(u32)]),
@@ -185,6 +188,24 @@ def sample_replacement(n: int, N: int, seed: int, out=None, stream=None, n0=None
                                          _stream_handle(stream))
     _check(rc, "dcs_sample_replacement_ex")
     return out
+
+
+def sample_part(n: int, N: int, seed: int, depth: int, index: int, out=None, capacity=None,
+                count_rank=None, variant: int = 0, stream=None, n0=None, dense_ratio=None):
+    """Part `index` of the depth-`depth` cut of the sample (variant 0: without
+    replacement, 1: with replacement).  Returns (out, count_rank): out holds
+    the part's values from element 0 when they fit `capacity`; count_rank is
+    a 2-element int64 CUDA tensor (count, rank in the full sample)."""
+    import torch
+    if capacity is None:
+        capacity = out.numel() if out is not None else n
+    out = _out_tensor(out, capacity)
+    if count_rank is None:
+        count_rank = torch.zeros(2, dtype=torch.int64, device="cuda")
+    rc = lib().dcs_sample_part(variant, n, N, seed, _params(n0, dense_ratio), depth, index,
+                               _ptr(out), capacity, _ptr(count_rank), _stream_handle(stream))
+    _check(rc, "dcs_sample_part")
+    return out, count_rank
 
 
 def bernoulli_capacity_hint(p: float, N: int) -> int:

@@ -307,7 +307,7 @@ void timing_end(hipStream_t s, Timing* t) {
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors, uint32_t leaf_wgs_per_cu) {
+                          bool register_errors, uint32_t leaf_wgs_per_cu, uint64_t* part_out) {
   if (leaf_cap >= dcs::kMaxLeafJobs) return DCS_ENOMEM;
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
@@ -321,7 +321,8 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   timing_begin(1, s, &t1);
-  e = dcs::launch_tree_top(inst, n_inst, top_threads, frontier, leaves, leaf_cap, ctl, s);
+  e = dcs::launch_tree_top(inst, n_inst, top_threads, frontier, leaves, leaf_cap, ctl, part_out,
+                           s);
   if (e == hipSuccess)
     e = dcs::launch_tree(inst, n_inst, threads, frontier, leaves, leaf_cap, stacks, stack_depth,
                          ctl, s);
@@ -442,6 +443,53 @@ int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed, const d
                                   uint64_t* out_dev, void* workspace, size_t ws_bytes,
                                   void* stream) {
   return sample_tree(1, n, N, seed, params, out_dev, workspace, ws_bytes, stream);
+}
+
+int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
+                        const dcs_params* params, uint32_t depth, uint64_t index,
+                        uint64_t* out_dev, uint64_t capacity, uint64_t* count_rank_dev,
+                        void* stream) {
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (variant != 0 && variant != 1) return DCS_EINVAL;
+  if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (variant == 0 && n > N) return DCS_EINVAL;
+  if (variant == 1 && N == 0 && n > 0) return DCS_EINVAL;
+  if (depth > DCS_MAX_PART_DEPTH || index >= (1ull << depth)) return DCS_EINVAL;
+  if (count_rank_dev == nullptr || (capacity > 0 && out_dev == nullptr)) return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  // Plan the part's subtree for at most min(n, capacity) values over the
+  // largest range a depth-`depth` node can have (ranges halve with the
+  // right child taking the odd element); at least one top path runs, so
+  // that the count and rank are always written.
+  const uint64_t range = ceil_div_pow2(N, depth);
+  uint64_t np = std::min(n, capacity);
+  if (variant == 0) np = std::min(np, range);
+  np = std::max<uint64_t>(np, 1);
+  const Plan pl = make_plan(np, std::max<uint64_t>(range, 1), P.n0, static_cast<uint32_t>(variant),
+                            cut_bias_for(static_cast<uint32_t>(variant), np));
+  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
+  void* ws = nullptr;
+  rc = own_workspace(c, L.total, &ws);
+  if (rc) return rc;
+  Instance I{};
+  I.n = n;
+  I.N = N;
+  I.seed = seed;
+  I.n0 = P.n0;
+  I.dense_ratio = P.dense_ratio;
+  I.variant = static_cast<uint32_t>(variant);
+  I.cut = depth + pl.cut;
+  I.top_cut = depth + pl.top_cut;
+  I.part_depth = depth;
+  I.part = index;
+  I.part_cap = capacity;
+  return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.top_threads, pl.leaf_cap,
+                           pl.stack_depth, out_dev, static_cast<hipStream_t>(stream), true,
+                           leaf_wgs_for(c, static_cast<uint32_t>(variant), np), count_rank_dev);
 }
 
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N) {

@@ -84,7 +84,8 @@ int32_t device_ctx(DeviceCtx** out);
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors, uint32_t leaf_wgs_per_cu);
+                          bool register_errors, uint32_t leaf_wgs_per_cu,
+                          uint64_t* part_out = nullptr);
 
 }  // namespace host
 }  // namespace dcs

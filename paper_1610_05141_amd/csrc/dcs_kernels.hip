@@ -1307,20 +1307,70 @@ __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uin
   return true;
 }
 
+// The root of part `part` of a sample cut at depth dp (Sec. 4.1, online
+// sampling): the depth-dp node on the path that the bits of `part` choose,
+// most significant first.  A path that ends above dp at a leaf gives that
+// leaf to the leftmost part below it (the remaining bits all zero) and
+// leaves the other parts empty, with rank after the leaf's values; an empty
+// node gives an empty part.  On return v.nv is the part's count and v.off
+// its rank (values of the sample in earlier parts); returns false when the
+// part is a leaf above dp or empty.
+__device__ __forceinline__ bool part_root(Node& v, uint32_t dp, uint64_t part,
+                                          const Instance& I) {
+  for (uint32_t d = 0; d < dp; ++d) {
+    if (v.nv == 0) return false;
+    if (is_leaf(v, I)) {
+      const uint32_t below = dp - d;
+      if ((part & ((1ull << below) - 1)) != 0) {
+        v.off += v.nv;
+        v.nv = 0;
+      }
+      return false;
+    }
+    const uint64_t L = split_left<true>(v, I);
+    const uint64_t l = v.Nv >> 1;
+    if ((part >> (dp - 1 - d)) & 1) {
+      v = Node{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
+    } else {
+      v = Node{2 * v.id, v.lo, l, L, v.off};
+    }
+  }
+  return true;
+}
+
 // One wave per top path (top_threads paths, 64 lanes each): the splits
 // above the frontier form the longest chain of the tree, and a wave finds
-// each split's accepted attempt in one round of 64.
+// each split's accepted attempt in one round of 64.  In part mode every
+// path first walks to the part's root (the same splits on every path),
+// the first path reports the part's count and rank, and offsets below
+// count from the part's first value.
 __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ inst,
                                                   uint32_t n_inst, uint64_t top_threads,
                                                   Node* frontier, Leaf* leaves, uint64_t leaf_cap,
-                                                  Control* ctl) {
+                                                  Control* ctl, uint64_t* part_out) {
   const uint64_t t = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   if (t >= top_threads) return;  // whole waves
   const Instance I = inst[find_instance(inst, n_inst, t, true)];
   const uint64_t g = t - I.top_base;
+  const bool lane0 = (threadIdx.x & 63u) == 0;
   Node v{1, 0, I.N, I.n, 0};
-  if (!walk_path<true>(v, 0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
-  if ((threadIdx.x & 63u) == 0) frontier[t] = v;
+  uint32_t d0 = 0;
+  if (part_out != nullptr) {
+    const bool inner = part_root(v, I.part_depth, I.part, I);
+    if (g == 0 && lane0) {
+      part_out[0] = v.nv;
+      part_out[1] = v.off;
+    }
+    v.off = 0;
+    if (v.nv > I.part_cap) v.nv = 0;  // the caller's buffer is too small
+    if (!inner) {
+      if (v.nv > 0 && g == 0 && lane0) emit(v, I, leaves, leaf_cap, ctl);
+      v.nv = 0;
+    }
+    d0 = I.part_depth;
+  }
+  if (v.nv > 0 && !walk_path<true>(v, d0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
+  if (lane0) frontier[t] = v;
 }
 
 __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
@@ -1811,11 +1861,11 @@ int bern_occupancy() {
 
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
-                           hipStream_t stream) {
+                           uint64_t* part_out, hipStream_t stream) {
   if (top_threads == 0) return hipSuccess;
   const uint64_t blocks = (top_threads * 64 + 255) / 256;  // one wave per path
   hipLaunchKernelGGL(k_tree_top, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
-                     n_inst, top_threads, frontier, leaves, leaf_cap, ctl);
+                     n_inst, top_threads, frontier, leaves, leaf_cap, ctl, part_out);
   return hipGetLastError();
 }
 

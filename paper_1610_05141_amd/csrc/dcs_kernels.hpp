@@ -20,7 +20,12 @@ struct Instance {
   uint32_t variant;     // 0 without replacement, 1 with replacement
   uint32_t cut;         // Algorithm P depth: 2^cut tree threads
   uint32_t top_cut;     // depth of the frontier the top kernel computes (<= cut)
-  uint32_t pad;
+  // Part mode (part_depth > 0): only the subtree of the depth-part_depth
+  // node `part` is sampled, with offsets counted from its first value; cut
+  // and top_cut then count from the root and include part_depth.
+  uint32_t part_depth;
+  uint64_t part;
+  uint64_t part_cap;    // nothing is sampled if the part holds more values
 };
 
 // A recursion-tree node (Fig. 1): node id (root 1, children 2i, 2i+1), the
@@ -97,9 +102,10 @@ int bern_occupancy();
 int bern_wave_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
 // frontier (written to `frontier`, one slot per top thread).
+// part_out (part mode only, else null): receives the part's count and rank.
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
-                           hipStream_t stream);
+                           uint64_t* part_out, hipStream_t stream);
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
                        uint32_t stack_depth, Control* ctl, hipStream_t stream);

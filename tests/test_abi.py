@@ -46,3 +46,23 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         pass
     else:
         raise AssertionError("expected FileNotFoundError")
+
+
+def test_sample_part_rejects_bad_arguments_before_any_device_call():
+    import paper_1610_05141_amd as m
+    L = m.lib()
+    cr = ctypes.c_void_p(8)  # never dereferenced: every case fails its checks first
+    out = ctypes.c_void_p(16)
+    cases = [
+        (2, 10, 100, 1, 0, 0, out, 10, cr),       # no such variant
+        (0, 101, 100, 1, 0, 0, out, 10, cr),      # n > N without replacement
+        (1, 5, 0, 1, 0, 0, out, 10, cr),          # empty universe with replacement
+        (0, 10, 2**52 + 1, 1, 0, 0, out, 10, cr), # universe too large
+        (0, 10, 100, 1, 46, 0, out, 10, cr),      # depth beyond the maximum
+        (0, 10, 100, 1, 3, 8, out, 10, cr),       # index >= 2^depth
+        (0, 10, 100, 1, 3, 1, out, 10, None),     # no count/rank buffer
+        (0, 10, 100, 1, 3, 1, None, 10, cr),      # no output with capacity > 0
+    ]
+    for variant, n, N, seed, depth, index, o, cap, c in cases:
+        rc = L.dcs_sample_part(variant, n, N, seed, None, depth, index, o, cap, c, None)
+        assert rc == m.DCS_EINVAL, (variant, n, N, depth, index)

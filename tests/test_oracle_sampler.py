@@ -296,3 +296,54 @@ def test_replacement_invariants(ref):
     obs = np.bincount((s - 1) * 50 // N, minlength=50)
     probs = np.array([((i + 1) * N + 49) // 50 - (i * N + 49) // 50 for i in range(50)]) / N
     assert _chisq_pvalue(obs, probs) > 1e-4
+
+
+# Online sampling in parts (Sec. 4.1): the parts of one cut, in index order,
+# concatenate to the full sample, and each rank is the number of values in
+# the parts before it.  (n, N, seed, n0, depth, variant): small n0 makes
+# leaves end paths above the cut (leftmost-part rule) and empty nodes occur.
+PART_CASES = [
+    (50000, 1 << 30, 3, 256, 0, 0),
+    (50000, 1 << 30, 3, 256, 4, 0),
+    (50000, 1 << 30, 3, 256, 10, 0),    # most paths end at leaves above the cut
+    (3000, 3100, 5, 64, 6, 0),          # dense leaves
+    (777, 10**9 + 7, 6, 16, 8, 0),      # ragged ranges
+    (5, 40, 7, 2, 5, 0),                # empty nodes above the cut
+    (40000, 1 << 36, 8, 512, 7, 1),     # with replacement
+    (3000, 7, 9, 64, 4, 1),             # with replacement, N_v = 1 leaves
+]
+
+
+@pytest.mark.parametrize("n,N,seed,n0,depth,variant", PART_CASES)
+def test_parts_concatenate_to_the_sample(ref, n, N, seed, n0, depth, variant):
+    full = ref.sample(n, N, seed, n0=n0) if variant == 0 else ref.replacement(n, N, seed, n0=n0)
+    got, rank = [], 0
+    for g in range(1 << depth):
+        vals, count, r = ref.part(variant, n, N, seed, depth, g, n0=n0)
+        assert r == rank, (g, r, rank)
+        assert len(vals) == count
+        got.append(vals)
+        rank += count
+    assert rank == n
+    assert (np.concatenate(got) == full).all()
+
+
+def test_part_depth_one_is_the_root_split(ref):
+    n, N, seed = 100000, 1 << 40, 11
+    left = ref.hyp(n, N // 2, N, seed, 1)
+    _, c0, r0 = ref.part(0, n, N, seed, 1, 0)
+    vals, c1, r1 = ref.part(0, n, N, seed, 1, 1)
+    assert (c0, r0, c1, r1) == (left, 0, n - left, left)
+    assert int(vals.min()) > N // 2  # the right half's range N/2+1 .. N
+
+
+def test_part_leaf_above_the_cut_and_overflow(ref):
+    n, N, seed = 100, 1 << 20, 4
+    full = ref.sample(n, N, seed)  # the root is a leaf (n < n0 = 4096)
+    vals, count, rank = ref.part(0, n, N, seed, 3, 0)
+    assert (count, rank) == (n, 0) and (vals == full).all()
+    for g in range(1, 8):
+        vals, count, rank = ref.part(0, n, N, seed, 3, g)
+        assert (count, rank, len(vals)) == (0, n, 0)
+    vals, count, rank = ref.part(0, n, N, seed, 0, 0, capacity=n - 1)
+    assert vals is None and (count, rank) == (n, 0)
