@@ -205,6 +205,66 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
     return res
 
 
+def bench_parts(dcs, depths=(4, 8), reps: int = 3):
+    """Online sampling in parts (Sec. 4.1): the n = 2^30 of 2^48 sample
+    produced part by part, all 2^d parts of the depth-d cut in order, into
+    one reused buffer (a streaming consumer's memory bound), against the
+    whole sample in one call."""
+    import torch
+    stream = torch.cuda.current_stream()
+    n, N, seed = N_SAMPLE, UNIVERSE, SEED
+    res = {"workload": f"without-replacement sample n=2^30 of N=2^48, seed={seed}, "
+                       "streamed part by part"}
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    dcs.sample(n, N, seed, out=out, stream=stream, n0=N0)
+    dcs.synchronize(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dcs.sample(n, N, seed, out=out, stream=stream, n0=N0)
+    dcs.synchronize(stream)
+    plain_ms = (time.perf_counter() - t0) / reps * 1e3
+    del out
+    torch.cuda.empty_cache()
+    res["plain_ms"] = plain_ms
+    cr = torch.zeros(2, dtype=torch.int64, device="cuda")
+    for d in depths:
+        per = n >> d
+        cap = per + per // 8 + (1 << 16)
+        buf = torch.empty(cap, dtype=torch.int64, device="cuda")
+
+        def sweep():
+            for g in range(1 << d):
+                dcs.sample_part(n, N, seed, d, g, out=buf, capacity=cap, count_rank=cr,
+                                stream=stream, n0=N0)
+
+        sweep()
+        dcs.synchronize(stream)
+        dcs.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sweep()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / reps
+        t_ms, t_n = dcs.profile_read(1)
+        l_ms, l_n = dcs.profile_read(2)
+        dcs.profile_enable(False)
+        count, rank = (int(x) for x in cr.cpu())
+        res[f"depth_{d}"] = {
+            "parts": 1 << d,
+            "buffer_bytes": 8 * cap,
+            "ms_all_parts": dt * 1e3,
+            "ms_per_part": dt * 1e3 / (1 << d),
+            "samples_per_s": n / dt,
+            "tree_ms_per_part": t_ms / max(t_n, 1),
+            "leaf_ms_per_part": l_ms / max(l_n, 1),
+            "vs_one_call": plain_ms / (dt * 1e3),
+            "last_part_ends_at_n": count + rank == n,
+        }
+        del buf
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(dcs, rate: float = 20000.0, warm: int = 10000, timed: int = 100000):
     """Open-loop Poisson arrivals at `rate`/s of instances drawn like the
     batched workload (n capped at 2^24), admitted by output footprint under a
@@ -252,9 +312,10 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-parts", action="store_true")
     ap.add_argument("--only", default=None,
                     help="comma list of other configurations (c1, c2b, c3a, c3b, batched, "
-                         "serving) to run alone, e.g. under a profiler; prints their lines only")
+                         "parts, serving) to run alone, e.g. under a profiler; prints their lines only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -268,11 +329,13 @@ def main() -> int:
     if args.only:
         names = args.only.split(",")
         res = {}
-        other = [x for x in names if x not in ("batched", "serving")]
+        other = [x for x in names if x not in ("batched", "serving", "parts")]
         if other:
             res.update(bench_other_configs(dcs, reps=args.steps, only=other))
         if "batched" in names:
             res["batched"] = bench_batched(dcs)
+        if "parts" in names:
+            res["parts"] = bench_parts(dcs)
         if "serving" in names:
             res["serving"] = bench_serving(dcs)
         print(json.dumps(res), flush=True)
@@ -372,6 +435,9 @@ def main() -> int:
     if not args.no_batched:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         rec["batched"] = bench_batched(dcs)
+    if not args.no_parts:
+        print("[bench] online parts", file=sys.stderr, flush=True)
+        rec["parts"] = bench_parts(dcs)
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         rec["serving"] = bench_serving(dcs)
