@@ -265,6 +265,51 @@ def bench_parts(dcs, depths=(4, 8), reps: int = 3):
     return res
 
 
+def bench_graph(dcs, reps: int = 5):
+    """Random graphs (Sec. 7): G(n, m) with m = 2^28 edges on n = 2^26
+    vertices, and G(n, p) on the same vertices with p = 2^-23 (2^28 edges
+    expected): whole-call edges/s, and the in-place index decoding kernel
+    against HBM (8 B read + 8 B written per edge)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    n, m, seed = 1 << 26, 1 << 28, 7
+    p = 2.0 ** -23
+    res = {"workload": f"G(n, m) and G(n, p) on n=2^26 vertices, m=2^28, p=2^-23, seed={seed}"}
+    e = torch.empty((m, 2), dtype=torch.int32, device="cuda")
+    N = n * (n - 1) // 2
+    cap = dcs.bernoulli_capacity_hint(p, N)
+    eg = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cases = {
+        "gnm": (lambda: dcs.sample_edges_gnm(n, m, seed, out=e, stream=stream), None),
+        "gnp": (lambda: dcs.sample_edges_gnp(n, p, seed, out=eg, capacity=cap, count=cnt,
+                                             stream=stream), cnt),
+    }
+    for name, (run, count) in cases.items():
+        run()
+        dcs.synchronize(stream)
+        dcs.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / reps
+        d_ms, d_n = dcs.profile_read(7)
+        dcs.profile_enable(False)
+        edges = m if count is None else int(count.item())
+        dec = d_ms / max(d_n, 1)
+        res[name] = {
+            "edges": edges,
+            "ms_per_call": dt * 1e3,
+            "edges_per_s": edges / dt,
+            "decode_kernel_ms": dec,
+            "decode_GBs": 16 * edges / (dec * 1e-3) / 1e9 if dec > 0 else None,
+        }
+    del e, eg
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(dcs, rate: float = 20000.0, warm: int = 10000, timed: int = 100000):
     """Open-loop Poisson arrivals at `rate`/s of instances drawn like the
     batched workload (n capped at 2^24), admitted by output footprint under a
@@ -313,9 +358,10 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-parts", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--only", default=None,
                     help="comma list of other configurations (c1, c2b, c3a, c3b, batched, "
-                         "parts, serving) to run alone, e.g. under a profiler; prints their lines only")
+                         "parts, graph, serving) to run alone, e.g. under a profiler; prints their lines only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -329,13 +375,15 @@ def main() -> int:
     if args.only:
         names = args.only.split(",")
         res = {}
-        other = [x for x in names if x not in ("batched", "serving", "parts")]
+        other = [x for x in names if x not in ("batched", "serving", "parts", "graph")]
         if other:
             res.update(bench_other_configs(dcs, reps=args.steps, only=other))
         if "batched" in names:
             res["batched"] = bench_batched(dcs)
         if "parts" in names:
             res["parts"] = bench_parts(dcs)
+        if "graph" in names:
+            res["graph"] = bench_graph(dcs)
         if "serving" in names:
             res["serving"] = bench_serving(dcs)
         print(json.dumps(res), flush=True)
@@ -438,6 +486,9 @@ def main() -> int:
     if not args.no_parts:
         print("[bench] online parts", file=sys.stderr, flush=True)
         rec["parts"] = bench_parts(dcs)
+    if not args.no_graph:
+        print("[bench] random graphs", file=sys.stderr, flush=True)
+        rec["graph"] = bench_graph(dcs)
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         rec["serving"] = bench_serving(dcs)

@@ -136,6 +136,37 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
                         uint64_t* out_dev, uint64_t capacity, uint64_t* count_rank_dev,
                         void* stream);
 
+/*
+ * dcs_sample_edges_gnm -- the edges of a uniform random graph G(n, m) on the
+ * vertices 0..n_vertices-1 (Sec. 7: such a graph is a sample without
+ * replacement of m of the n(n-1)/2 possible edges).  Edge index k (0-based)
+ * is the pair (u, v), v < u, with k = u(u-1)/2 + v; the edges are those of
+ * dcs_sample_ex(m, n(n-1)/2, seed, params) (value k+1 <-> index k), decoded
+ * in place.
+ *   uv_dev: 2m uint32 in device memory, 8-byte aligned: edge i is
+ *           (uv_dev[2i], uv_dev[2i+1]) = (u, v), in increasing (u, v) order.
+ * Errors: DCS_EINVAL if n(n-1)/2 > DCS_MAX_UNIVERSE, m > n(n-1)/2, uv_dev
+ * NULL or not 8-byte aligned with m > 0, or bad params.
+ */
+int32_t dcs_sample_edges_gnm(uint64_t n_vertices, uint64_t m, uint64_t seed,
+                             const dcs_params* params, uint32_t* uv_dev, void* stream);
+/*
+ * dcs_sample_edges_gnp -- the edges of a random graph G(n, p): each of the
+ * n(n-1)/2 pairs independently with probability p (Sec. 7: Bernoulli
+ * sampling of the possible edges), i.e. dcs_sample_bernoulli_ex over
+ * 1..n(n-1)/2 decoded as for G(n, m).
+ *   uv_dev:    2 * capacity uint32 (8-byte aligned); the first
+ *              min(count, capacity) edges are written.
+ *   count_dev: one uint64 in device memory, receives the true edge count
+ *              (compare with capacity after synchronizing, as for
+ *              dcs_sample_bernoulli).
+ * Errors: as dcs_sample_bernoulli, plus DCS_EINVAL if n(n-1)/2 >
+ * DCS_MAX_UNIVERSE or uv_dev is not 8-byte aligned.
+ */
+int32_t dcs_sample_edges_gnp(uint64_t n_vertices, double p, uint64_t seed,
+                             const dcs_params* params, uint32_t* uv_dev, uint64_t capacity,
+                             uint64_t* count_dev, void* stream);
+
 /* A capacity that the Bernoulli count exceeds with negligible probability:
  * Np + 10 sqrt(Np(1-p)) + 64. */
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N);
@@ -276,8 +307,8 @@ const char* dcs_status_string(int32_t status);
  * 3 = Bernoulli chunk, 4 = leaf kernel of the sparse and with-replacement
  * jobs over power-of-two ranges,
  * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
- * kernel of the dense jobs with ranges up to 2^16); DCS_EINVAL for another
- * kind. */
+ * kernel of the dense jobs with ranges up to 2^16, 7 = edge-index
+ * decoding of the graph entry points); DCS_EINVAL for another kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 /* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind

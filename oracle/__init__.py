@@ -64,6 +64,9 @@ def configure(L: ctypes.CDLL) -> ctypes.CDLL:
             "dcs_ref_part": (i32, [i32, u64, u64, u64, u32, u32, u32, u64, p64, u64, p64,
                                    p64]),
             "dcs_ref_bernoulli": (i32, [dbl, u64, u64, u32, p64, u64, p64]),
+            "dcs_ref_edge_pair": (None, [u64, p64]),
+            "dcs_ref_edges_gnm": (i32, [u64, u64, u64, u32, p32]),
+            "dcs_ref_edges_gnp": (i32, [u64, dbl, u64, u32, p32, u64, p64]),
             "dcs_ref_bernoulli_chunks": (i32, [dbl, u64, u64, u32, u64, u64, p64, u64, p64]),
             "dcs_ref_bernoulli_chunk_len": (u64, [dbl, u32]),
             "dcs_ref_philox": (None, [p32, p32, p32]),
@@ -154,6 +157,34 @@ def part(variant: int, n: int, N: int, seed: int, depth: int, index: int,
         return None, count, r
     _check(rc, "part")
     return out[:count].copy(), count, r
+
+
+def edge_pair(k: int) -> tuple:
+    """(u, v), v < u, of edge index k = u(u-1)/2 + v (Sec. 7 random graphs)."""
+    out = np.zeros(2, dtype=np.uint64)
+    lib().dcs_ref_edge_pair(k, _p64(out))
+    return int(out[0]), int(out[1])
+
+
+def edges_gnm(n_vertices: int, m: int, seed: int, n0: int = DEFAULT_N0) -> np.ndarray:
+    """G(n, m) edge list, (m, 2) uint32 rows (u, v), in increasing order."""
+    uv = np.zeros((max(m, 1), 2), dtype=np.uint32)
+    _check(lib().dcs_ref_edges_gnm(n_vertices, m, seed, n0,
+                                   uv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))),
+           "edges_gnm")
+    return uv[:m]
+
+
+def edges_gnp(n_vertices: int, p: float, seed: int, n0: int = DEFAULT_N0,
+              capacity: int = 1 << 20) -> np.ndarray:
+    """G(n, p) edge list (all of it; capacity must hold it)."""
+    uv = np.zeros((max(capacity, 1), 2), dtype=np.uint32)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().dcs_ref_edges_gnp(n_vertices, float(p), seed, n0,
+                                 uv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), capacity,
+                                 _p64(cnt))
+    _check(rc, "edges_gnp")
+    return uv[: int(cnt[0])].copy()
 
 
 def bernoulli(p: float, N: int, seed: int, n0: int = DEFAULT_N0,

@@ -784,6 +784,65 @@ EXPORT int dcs_ref_part(int variant, uint64_t n, uint64_t N, uint64_t seed, uint
                       : sample_r(&c, id, lo, Nv, nv, off, &k);
 }
 
+/* Random graphs (Sec. 7): G(n, m) samples m of the n(n-1)/2 possible edges
+ * without replacement, G(n, p) takes each with probability p.  Edge index k
+ * (0-based) is the pair (u, v), v < u, with k = u(u-1)/2 + v, i.e. u is the
+ * unique integer with u(u-1)/2 <= k < u(u+1)/2.  Since 8k+1 then lies in
+ * [(2u-1)^2, (2u+1)^2), u = (1 + isqrt(8k+1)) / 2 (integer square root). */
+static void edge_pair(uint64_t k, uint64_t *u, uint64_t *v) {
+  uint64_t r = isqrt_u64(8 * k + 1);
+  *u = (1 + r) / 2;
+  *v = k - *u * (*u - 1) / 2;
+}
+
+static int edge_count(uint64_t n_vertices, uint64_t *N) {
+  if (n_vertices > (1ULL << 32)) return REF_EINVAL;
+  *N = n_vertices < 2 ? 0 : n_vertices * (n_vertices - 1) / 2;
+  return *N > REF_MAX_N ? REF_EINVAL : REF_OK;
+}
+
+static void decode_edges(const uint64_t *vals, uint64_t count, uint32_t *uv) {
+  for (uint64_t i = 0; i < count; ++i) {
+    uint64_t u, v;
+    edge_pair(vals[i] - 1, &u, &v);
+    uv[2 * i] = (uint32_t)u;
+    uv[2 * i + 1] = (uint32_t)v;
+  }
+}
+
+EXPORT void dcs_ref_edge_pair(uint64_t k, uint64_t out[2]) { edge_pair(k, &out[0], &out[1]); }
+
+EXPORT int dcs_ref_edges_gnm(uint64_t n_vertices, uint64_t m, uint64_t seed, uint32_t n0,
+                             uint32_t *uv) {
+  uint64_t N;
+  if (edge_count(n_vertices, &N) != REF_OK || m > N) return REF_EINVAL;
+  if (m == 0) return REF_OK;
+  uint64_t *vals = (uint64_t *)malloc(m * sizeof(uint64_t));
+  if (!vals) return REF_ENOMEM;
+  int rc = dcs_ref_sample(m, N, seed, n0, 16, vals);
+  if (rc == REF_OK) decode_edges(vals, m, uv);
+  free(vals);
+  return rc;
+}
+
+EXPORT int dcs_ref_bernoulli(double p, uint64_t N, uint64_t seed, uint32_t n0,
+                             uint64_t *out, uint64_t capacity, uint64_t *count);
+
+EXPORT int dcs_ref_edges_gnp(uint64_t n_vertices, double p, uint64_t seed, uint32_t n0,
+                             uint32_t *uv, uint64_t capacity, uint64_t *count) {
+  uint64_t N;
+  if (count == NULL) return REF_EINVAL;
+  *count = 0;
+  if (edge_count(n_vertices, &N) != REF_OK) return REF_EINVAL;
+  uint64_t *vals = (uint64_t *)malloc((capacity ? capacity : 1) * sizeof(uint64_t));
+  if (!vals) return REF_ENOMEM;
+  int rc = dcs_ref_bernoulli(p, N, seed, n0, vals, capacity, count);
+  if (rc == REF_OK || rc == REF_EOVERFLOW)
+    decode_edges(vals, *count < capacity ? *count : capacity, uv);
+  free(vals);
+  return rc;
+}
+
 /* Bernoulli sample of 1..N with probability p, chunks [jC, (j+1)C) sampled
  * independently with their own streams.  Writes the first `capacity` values
  * to out and the true count to *count.  Chunks [c0, c1) only when

@@ -14,6 +14,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "sample_part",
+    "sample_edges_gnm", "sample_edges_gnp",
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
@@ -29,7 +30,7 @@ DCS_OK, DCS_EINVAL, DCS_ENOMEM, DCS_EHIP, DCS_EOVERFLOW, DCS_EDEVICE, DCS_ENOTSU
 EXPORTED_SYMBOLS = (
     "dcs_sample", "dcs_sample_ex", "dcs_sample_replacement", "dcs_sample_replacement_ex",
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
-    "dcs_sample_part",
+    "dcs_sample_part", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
     "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
@@ -94,6 +95,8 @@ def lib() -> ctypes.CDLL:
                                               ctypes.c_size_t, vp]),
             "dcs_bernoulli_capacity_hint": (u64, [dbl, u64]),
             "dcs_sample_part": (i32, [i32, u64, u64, u64, pp, u32, u64, vp, u64, vp, vp]),
+            "dcs_sample_edges_gnm": (i32, [u64, u64, u64, pp, vp, vp]),
+            "dcs_sample_edges_gnp": (i32, [u64, dbl, u64, pp, vp, u64, vp, vp]),
             "dcs_workspace_size": (i32, [i32, u64, u64, dbl, pp, ctypes.POINTER(ctypes.c_size_t)]),
             "dcs_batch_create": (i32, [ctypes.POINTER(_Instance), u32, ctypes.POINTER(vp),
                                        ctypes.POINTER(u32)]),
@@ -206,6 +209,45 @@ def sample_part(n: int, N: int, seed: int, depth: int, index: int, out=None, cap
                                _ptr(out), capacity, _ptr(count_rank), _stream_handle(stream))
     _check(rc, "dcs_sample_part")
     return out, count_rank
+
+
+def _edge_tensor(out, m: int):
+    import torch
+    if out is None:
+        return torch.empty((max(m, 0), 2), dtype=torch.int32, device="cuda")
+    if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() or \
+            out.numel() < 2 * m:
+        raise ValueError(f"out must be a contiguous int32 CUDA tensor of {2 * m} elements")
+    return out
+
+
+def sample_edges_gnm(n_vertices: int, m: int, seed: int, out=None, stream=None, n0=None):
+    """G(n, m): m distinct edges (u, v), v < u < n_vertices, as an (m, 2) int32
+    CUDA tensor in increasing (u, v) order (values are below 2^31 for any
+    n_vertices the library accepts)."""
+    out = _edge_tensor(out, m)
+    rc = lib().dcs_sample_edges_gnm(n_vertices, m, seed, _params(n0, None), _ptr(out),
+                                    _stream_handle(stream))
+    _check(rc, "dcs_sample_edges_gnm")
+    return out
+
+
+def sample_edges_gnp(n_vertices: int, p: float, seed: int, out=None, capacity=None, count=None,
+                     stream=None, n0=None):
+    """G(n, p): each pair an edge with probability p.  Returns (edges, count):
+    edges is an (capacity, 2) int32 CUDA tensor whose first min(count,
+    capacity) rows hold the edges; count a 1-element int64 CUDA tensor."""
+    import torch
+    N = n_vertices * (n_vertices - 1) // 2
+    if capacity is None:
+        capacity = out.numel() // 2 if out is not None else bernoulli_capacity_hint(p, N)
+    out = _edge_tensor(out, capacity)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc = lib().dcs_sample_edges_gnp(n_vertices, float(p), seed, _params(n0, None), _ptr(out),
+                                    capacity, _ptr(count), _stream_handle(stream))
+    _check(rc, "dcs_sample_edges_gnp")
+    return out, count
 
 
 def bernoulli_capacity_hint(p: float, N: int) -> int:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libdcs.so")
-SOURCES = ["dcs_kernels.hip", "dcs_api.hip", "dcs_server.hip"]
+SOURCES = ["dcs_kernels.hip", "dcs_api.hip", "dcs_server.hip", "dcs_graph.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -180,12 +180,6 @@ double host_log1p_series(double x) {
 }
 
 // ---- device context -------------------------------------------------------
-struct Timing {
-  int kind;
-  int dev;
-  hipEvent_t a, b;  // a == nullptr: this launch is not timed
-};
-
 
 std::mutex g_mu;
 std::vector<DeviceCtx> g_dev;
@@ -216,8 +210,8 @@ void release_timings() {
 }
 // kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
 // 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
-// the rest, 6 one-wave dense leaf kernel
-constexpr int kProfKinds = 7;
+// the rest, 6 one-wave dense leaf kernel, 7 edge-index decoding
+constexpr int kProfKinds = 8;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 

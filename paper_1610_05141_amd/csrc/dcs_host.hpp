@@ -87,5 +87,14 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
                           bool register_errors, uint32_t leaf_wgs_per_cu,
                           uint64_t* part_out = nullptr);
 
+// Kernel timing with pooled HIP events on the launch stream (dcs_profile_*):
+// kinds as listed at dcs_profile_read; caller holds lock().
+struct Timing {
+  int kind;
+  int dev;
+  hipEvent_t a, b;  // a == nullptr: this launch is not timed
+};
+void timing_begin(int kind, hipStream_t s, Timing* t);
+void timing_end(hipStream_t s, Timing* t);
 }  // namespace host
 }  // namespace dcs

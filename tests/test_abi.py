@@ -66,3 +66,19 @@ def test_sample_part_rejects_bad_arguments_before_any_device_call():
     for variant, n, N, seed, depth, index, o, cap, c in cases:
         rc = L.dcs_sample_part(variant, n, N, seed, None, depth, index, o, cap, c, None)
         assert rc == m.DCS_EINVAL, (variant, n, N, depth, index)
+
+
+def test_graph_entry_points_reject_bad_arguments_before_any_device_call():
+    import paper_1610_05141_amd as m
+    L = m.lib()
+    ok = ctypes.c_void_p(16)
+    odd = ctypes.c_void_p(12)  # not 8-byte aligned
+    cnt = ctypes.c_void_p(8)
+    assert L.dcs_sample_edges_gnm(94906267, 1, 1, None, ok, None) == m.DCS_EINVAL  # > 2^52 pairs
+    assert L.dcs_sample_edges_gnm(10, 46, 1, None, ok, None) == m.DCS_EINVAL       # m > 45 pairs
+    assert L.dcs_sample_edges_gnm(10, 5, 1, None, None, None) == m.DCS_EINVAL
+    assert L.dcs_sample_edges_gnm(10, 5, 1, None, odd, None) == m.DCS_EINVAL
+    assert L.dcs_sample_edges_gnm(10, 0, 1, None, None, None) == m.DCS_OK          # nothing to do
+    assert L.dcs_sample_edges_gnp(94906267, 0.5, 1, None, ok, 10, cnt, None) == m.DCS_EINVAL
+    assert L.dcs_sample_edges_gnp(10, 0.5, 1, None, odd, 10, cnt, None) == m.DCS_EINVAL
+    assert L.dcs_sample_edges_gnp(10, 0.5, 1, None, None, 10, cnt, None) == m.DCS_EINVAL
