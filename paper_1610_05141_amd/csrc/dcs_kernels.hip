@@ -1418,7 +1418,6 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
 __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table) {
   if (threadIdx.x == 0) {
     ctl->leaf_counts = 0;
-    ctl->chunk_ticket = 0;
     ctl->bern_count = 0;
     if (has_single) table[0] = single;
   }
@@ -1432,7 +1431,6 @@ __global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n,
   if (blockIdx.x == 0 && threadIdx.x < kTicketWords) tickets[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->leaf_counts = 0;
-    ctl->chunk_ticket = 0;
     ctl->bern_count = 0;
   }
 }
@@ -1563,17 +1561,26 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
   return acc;
 }
 
+// Chunks are handed out as in k_bern_wave: n_cls counters kTicketStride
+// words apart, work-group class c = blockIdx mod n_cls taking chunks c,
+// c + n_cls, ... in order (one shared counter serializes the hand-out at
+// about one chunk per same-address atomic; every class has a resident
+// work-group, so the look-back always progresses).
 __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
                                                      uint64_t n_chunks, double c64,
                                                      unsigned long long* status, uint64_t* out,
                                                      uint64_t capacity, uint64_t* count_dev,
-                                                     Control* ctl, uint32_t lds_cap) {
+                                                     Control* ctl, uint32_t lds_cap,
+                                                     unsigned long long* tickets,
+                                                     uint32_t n_cls) {
   __shared__ uint32_t pos[kBernLds];
   __shared__ uint64_t scr64[8];
   __shared__ uint32_t ends;
   __shared__ unsigned long long cur, excl;
+  const uint32_t cls = blockIdx.x % n_cls;
+  unsigned long long* const ticket = tickets + cls * kTicketStride;
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(&ctl->chunk_ticket, 1ull);
+    if (threadIdx.x == 0) cur = cls + atomicAdd(ticket, 1ull) * n_cls;
     __syncthreads();
     const unsigned long long j = cur;
     __syncthreads();
@@ -1908,7 +1915,7 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                        status, out, capacity, count_dev, ctl, tickets, n_cls);
   else
     hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk, n_chunks,
-                       c64, status, out, capacity, count_dev, ctl, lds_cap);
+                       c64, status, out, capacity, count_dev, ctl, lds_cap, tickets, n_cls);
   return hipGetLastError();
 }
 

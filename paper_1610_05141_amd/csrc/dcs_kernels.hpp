@@ -61,7 +61,7 @@ struct Control {
   // serves both
   unsigned long long leaf_counts;
   unsigned long long pad0;
-  unsigned long long chunk_ticket; // FP64 Bernoulli: next chunk to hand out
+  unsigned long long pad1;
   unsigned int error;              // latched error bits (kErr*)
   unsigned int pad;
   unsigned long long bern_count;   // Bernoulli: total hits (copied to the caller)
@@ -77,7 +77,7 @@ constexpr int kLeafBlock = 512;             // threads of a leaf work-group
 constexpr int kBernBlock = 256;             // threads of a Bernoulli work-group
 constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
 constexpr uint64_t kFillPiece = 1ull << 16; // constant-fill leaves are cut to this
-// Single-precision Bernoulli chunks are handed out by kTicketClasses
+// Bernoulli chunks (both kernels) are handed out by kTicketClasses
 // counters (7: coprime to the 8 XCDs), kTicketStride words apart.
 constexpr uint32_t kTicketClasses = 7;
 constexpr uint32_t kTicketStride = 32;

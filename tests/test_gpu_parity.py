@@ -160,6 +160,11 @@ BERN_CASES = [
     # chunks of 8192 with ~4096 hits: about half hold more hits than the
     # 4096 increments a wave keeps, and recompute their last group
     (0.5, 1 << 22, 21),
+    # double-precision skips over many chunks, handed out by all ticket
+    # classes: chunks clamped at 2^32 with ~512 hits each, and 128 chunks
+    # of 2^23 just below the single-precision threshold
+    (2.0**-23, 1 << 40, 31),
+    (2.0**-11, 1 << 30, 32),
 ]
 
 
