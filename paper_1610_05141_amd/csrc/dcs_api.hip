@@ -227,7 +227,6 @@ int32_t device_ctx(DeviceCtx** out) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DCS_EHIP;
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
-    c.bern_occupancy = dcs::bern_occupancy();
     c.bern_wave_occupancy = dcs::bern_wave_occupancy();
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
@@ -533,10 +532,22 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
   hipError_t e = dcs::launch_zero(ctl, status, n_chunks, tickets, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
-  const uint64_t occ = static_cast<uint64_t>(fp32 ? c->bern_wave_occupancy : c->bern_occupancy);
+  // LDS offsets per double-precision chunk: 2 n0 + 64, or fewer when a full
+  // chunk expects fewer hits (chunks clamped at 2^32 for small p); a chunk
+  // with more hits writes the rest in a second pass, so this choice never
+  // changes the sample, only how many work-groups stay resident.  The grid
+  // never exceeds the resident work-groups (the look-back needs them all).
+  uint32_t lds_cap = 2 * P.n0 + 64;
+  if (!fp32) {
+    const double m = static_cast<double>(chunk) * p;
+    const double want = m + 10.0 * sqrt(m) + 64.0;
+    if (want < static_cast<double>(lds_cap))
+      lds_cap = (static_cast<uint32_t>(want) + 63u) & ~63u;
+  }
+  const uint64_t occ =
+      static_cast<uint64_t>(fp32 ? c->bern_wave_occupancy : dcs::bern_occupancy(lds_cap));
   const uint32_t grid = static_cast<uint32_t>(
       std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * occ)));
-  const uint32_t lds_cap = 2 * P.n0 + 64;
   timing_begin(3, s, &t1);
   e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,
                             count_dev, ctl, tickets, grid, lds_cap, s);

@@ -45,7 +45,6 @@ struct DeviceCtx {
   bool init = false;
   int cus = 256;
   int leaf_occupancy = 2;
-  int bern_occupancy = 2;
   int bern_wave_occupancy = 8;
   int dense_occupancy = 8;
   // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets

@@ -1442,7 +1442,6 @@ constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagIncl = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 26;
-constexpr uint32_t kBernLds = kRegionA;  // holds lds_cap = 2 n0 + 64 <= 8256 offsets
 
 // Double-precision Bernoulli chunks (p < 2^-10), one work-group per chunk:
 // one pass over the chunk's geometric stream.  Hit k of the chunk sits at
@@ -1573,7 +1572,7 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
                                                      Control* ctl, uint32_t lds_cap,
                                                      unsigned long long* tickets,
                                                      uint32_t n_cls) {
-  __shared__ uint32_t pos[kBernLds];
+  extern __shared__ uint32_t pos[];  // lds_cap offsets (dynamic)
   __shared__ uint64_t scr64[8];
   __shared__ uint32_t ends;
   __shared__ unsigned long long cur, excl;
@@ -1857,12 +1856,13 @@ int bern_wave_occupancy() {
   return occ;
 }
 
-int bern_occupancy() {
+int bern_occupancy(uint32_t lds_cap) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &occ, reinterpret_cast<const void*>(k_bern), kBernBlock, 0) != hipSuccess ||
+          &occ, reinterpret_cast<const void*>(k_bern), kBernBlock,
+          static_cast<size_t>(lds_cap) * sizeof(uint32_t)) != hipSuccess ||
       occ <= 0)
-    occ = 2;
+    occ = 1;
   return occ;
 }
 
@@ -1914,8 +1914,10 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
     hipLaunchKernelGGL(k_bern_wave, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
                        status, out, capacity, count_dev, ctl, tickets, n_cls);
   else
-    hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock), 0, stream, N, seed, chunk, n_chunks,
-                       c64, status, out, capacity, count_dev, ctl, lds_cap, tickets, n_cls);
+    hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock),
+                       static_cast<size_t>(lds_cap) * sizeof(uint32_t), stream, N, seed, chunk,
+                       n_chunks, c64, status, out, capacity, count_dev, ctl, lds_cap, tickets,
+                       n_cls);
   return hipGetLastError();
 }
 

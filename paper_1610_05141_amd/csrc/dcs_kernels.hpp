@@ -97,8 +97,9 @@ int leaf_occupancy();
 // Resident k_leaf_dense work-groups (one wave each) per compute unit.
 int dense_occupancy();
 // Resident work-groups per compute unit of the double-precision Bernoulli
-// kernel, and of the one-wave single-precision one.
-int bern_occupancy();
+// kernel holding lds_cap offsets in LDS, and of the one-wave
+// single-precision one.
+int bern_occupancy(uint32_t lds_cap);
 int bern_wave_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
 // frontier (written to `frontier`, one slot per top thread).
