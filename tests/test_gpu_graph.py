@@ -67,3 +67,15 @@ def test_gnm_2p28_edges_on_2p26_vertices(ref):
     assert bool((v < u).all()) and bool((u < n).all()) and bool((v >= 0).all())
     key = u * n + v
     assert bool((key[1:] > key[:-1]).all())
+
+
+def test_graphs_without_pairs(ref):
+    """n_vertices 0 and 1 have no pairs: G(n, m) with m = 0, G(n, p) empty."""
+    mod = dcs()
+    announce("graphs without pairs")
+    for nv in (0, 1):
+        e = mod.sample_edges_gnm(nv, 0, 1)
+        assert e.shape[0] == 0
+        e, cnt = mod.sample_edges_gnp(nv, 0.5, 1)
+        mod.synchronize()
+        assert int(cnt.item()) == 0

@@ -101,3 +101,26 @@ def test_parts_of_the_8gib_sample(ref):
             want = ref.sample_window(n, N, seed, r + s, 4096)
             got = to_np_u64(buf[s:s + 4096])
             assert np.array_equal(got, want), f"part {g} at {s}: {first_mismatch(got, want)}"
+
+
+@pytest.mark.parametrize("n,N,depth,index,variant", [
+    (0, 100, 3, 5, 0),                   # empty sample: every part empty, rank 0
+    (0, 100, 0, 0, 1),
+    (200, 2**52, 45, 2**44 + 12345, 0),  # deepest cut, largest universe
+    (200, 2**52, 45, 0, 0),              # its leftmost part holds the leaf above the cut
+    (5000, 2**52, 40, 2**39, 1),         # with replacement, deep cut
+])
+def test_part_edge_cases(ref, n, N, depth, index, variant):
+    import torch
+    m = dcs()
+    announce(f"part edge n={n} N={N} depth={depth} index={index} variant={variant}")
+    buf = torch.full((max(n, 1),), -3, dtype=torch.int64, device="cuda")
+    cr = torch.full((2,), -1, dtype=torch.int64, device="cuda")
+    m.sample_part(n, N, 9, depth, index, out=buf, capacity=max(n, 1), count_rank=cr,
+                  variant=variant)
+    m.synchronize()
+    count, r = (int(x) for x in cr.cpu())
+    want, wc, wr = ref.part(variant, n, N, 9, depth, index, capacity=max(n, 1))
+    assert (count, r) == (wc, wr)
+    got = to_np_u64(buf[:count])
+    assert np.array_equal(got, want), first_mismatch(got, want)

@@ -347,3 +347,23 @@ def test_part_leaf_above_the_cut_and_overflow(ref):
         assert (count, rank, len(vals)) == (0, n, 0)
     vals, count, rank = ref.part(0, n, N, seed, 0, 0, capacity=n - 1)
     assert vals is None and (count, rank) == (n, 0)
+
+
+def test_part_edge_cases(ref):
+    for g in range(8):
+        vals, count, rank = ref.part(0, 0, 100, 1, 3, g)
+        assert (count, rank, len(vals)) == (0, 0, 0)
+    # the deepest cut of the largest universe: the range rule splits down to
+    # depth 20 (ranges of 2^32), where these 20 values sit in leaves; the leaf
+    # over range i (values i*2^32+1 .. (i+1)*2^32) goes whole to the leftmost
+    # depth-45 part below it, index i*2^25, and the part after it is empty
+    n, N, seed = 20, 2**52, 9
+    full = ref.sample(n, N, seed).astype(np.int64)
+    for i in sorted({int(v - 1) >> 32 for v in full}):
+        inside = full[(full - 1) >> 32 == i]
+        before = int(np.count_nonzero(((full - 1) >> 32) < i))
+        vals, count, rank = ref.part(0, n, N, seed, 45, i << 25)
+        assert (count, rank) == (len(inside), before)
+        assert (vals.astype(np.int64) == inside).all()
+        vals, count, rank = ref.part(0, n, N, seed, 45, (i << 25) + 1)
+        assert (count, rank) == (0, before + len(inside))
