@@ -39,7 +39,7 @@ typedef enum dcs_status {
   DCS_EHIP = 3,      /* a HIP runtime call failed */
   DCS_EOVERFLOW = 4, /* Bernoulli: more hits than `capacity` */
   DCS_EDEVICE = 5,   /* a kernel latched an error (reported at synchronize) */
-  DCS_ENOTSUP = 6    /* request outside what this build supports */
+  DCS_ENOTSUP = 6    /* request outside what the library supports */
 } dcs_status;
 
 /* Largest universe N accepted (every integer entering a double stays exact). */
