@@ -12,6 +12,11 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *     work is enqueued asynchronously on it; nothing blocks the host unless
  *     the entry point says so.
+ *   - Calls without a caller workspace (dcs_sample, the _ex forms with
+ *     workspace == NULL, dcs_sample_part, the graph entry points) share one
+ *     library workspace per device: calls on different streams must not
+ *     overlap in time (give concurrent streams their own workspaces through
+ *     the _ex forms, or use one stream).
  *   - Output values are 1-based (elements of 1..N) as uint64, ascending.
  *   - Return value: a dcs_status code.  Device-side failures (a capacity
  *     bound exceeded inside a kernel) cannot be returned by an asynchronous
