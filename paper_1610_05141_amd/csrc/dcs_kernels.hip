@@ -693,7 +693,9 @@ __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
   uint32_t key[kKeys / B];
   uint32_t live;
-  if (first_round_regs<B>(st, nv, ri, key, &live, sm) >= nv) {
+  const uint32_t got = first_round_regs<B>(st, nv, ri, key, &live, sm);
+  __builtin_amdgcn_s_setprio(2);  // the sort and its rounds ahead of other work-groups
+  if (got >= nv) {
     if (sort_registers<B, false, true>(key, nv, shift, nb, sm, live) != 0) {
       const uint64_t t = sm.scr[kScrNext];
       const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
@@ -703,6 +705,7 @@ __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
     // too many void words among the first W: the general rounds from word 0
     sparse_rounds<B>(st, 0, 0, nv, ri, shift, nb, sm);
   }
+  __builtin_amdgcn_s_setprio(0);
   write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
 
@@ -734,7 +737,14 @@ __device__ void leaf_sparse_pow2(const Leaf& L, uint64_t* out, LeafSmem& sm) {
       key[4 * k + 3] = w.w >> pshift;
     }
   }
-  if (sort_registers<B, true>(key, nv, shift, nb, sm) != 0 && !wr) {
+  // The sort is a chain of barrier-separated LDS phases; at raised issue
+  // priority its waves go ahead of other work-groups' Philox and store
+  // instructions, so a work-group spends less time waiting at its barriers
+  // (the stores and the next leaf's draws fill the gaps).
+  __builtin_amdgcn_s_setprio(2);
+  const uint32_t dups = sort_registers<B, true>(key, nv, shift, nb, sm);
+  __builtin_amdgcn_s_setprio(0);
+  if (dups != 0 && !wr) {
     const uint32_t have = compact_distinct<B>(sm.keys, sm.tmp, sm.scr, nv);
     sparse_rounds<B, true>(st, nv, have, nv, range_info(L.Nv), shift, nb, sm);
   }
@@ -752,7 +762,9 @@ __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const Stream st = make_stream(L.seed, L.id, kWrLeaf, 0);
   uint32_t key[kKeys / B];
   uint32_t live;
-  if (first_round_regs<B>(st, nv, ri, key, &live, sm) >= nv) {
+  const uint32_t got = first_round_regs<B>(st, nv, ri, key, &live, sm);
+  __builtin_amdgcn_s_setprio(2);  // the sort ahead of other work-groups
+  if (got >= nv) {
     sort_registers<B, false, true>(key, nv, shift, nb, sm, live);
   } else {
     uint32_t* keys = sm.keys;
@@ -761,6 +773,7 @@ __device__ void leaf_wr(const Leaf& L, uint64_t* out, LeafSmem& sm) {
     __syncthreads();
     sort_registers<B>(key, nv, shift, nb, sm);
   }
+  __builtin_amdgcn_s_setprio(0);
   write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
 }
 
