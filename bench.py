@@ -57,10 +57,31 @@ def recorded_traffic():
     return t["fetch_bytes"] + t["write_bytes"]
 
 
-def cpu_baseline(gpu_out, budget_s: float = 12.0):
-    """The oracle (single-threaded C) on a window of the same sample, sized
-    to about `budget_s` seconds; also checks the GPU's values there."""
+def host_description() -> dict:
+    """What the CPU baseline ran on: logical CPUs, those this process may
+    use, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": model}
+
+
+def cpu_baseline(gpu_out, budget_s: float = 12.0, max_threads: int = 16):
+    """The oracle (plain C) on a window of the same sample, sized to about
+    `budget_s` seconds on one thread; then the same window on all usable
+    cores (up to `max_threads`), split into consecutive sub-windows that
+    each thread computes on its own (each visits only the subtrees that
+    overlap it, so the pieces concatenate to the same values); also checks
+    the GPU's values there."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     oracle.build()
     # calibrate on a small window, then size the timed one
@@ -71,15 +92,27 @@ def cpu_baseline(gpu_out, budget_s: float = 12.0):
     start = (N_SAMPLE - count) // 2
     t0 = time.perf_counter()
     want = oracle.sample_window(N_SAMPLE, UNIVERSE, SEED, start, count)
-    dt = time.perf_counter() - t0
+    dt1 = time.perf_counter() - t0
+    threads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    bounds = [start + count * k // threads for k in range(threads + 1)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        pieces = list(ex.map(lambda k: oracle.sample_window(
+            N_SAMPLE, UNIVERSE, SEED, bounds[k], bounds[k + 1] - bounds[k]), range(threads)))
+    dtn = time.perf_counter() - t0
+    same = bool(np.array_equal(np.concatenate(pieces), want))
     got = gpu_out[start:start + count].cpu().numpy().view(np.uint64)
     return {
-        "value": count / dt,
+        "value": count / dtn,
         "unit": "samples/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": f"window of {count} consecutive outputs (offset {start}) of the same "
-                  f"n=2^30, N=2^48, seed=7 sample; {dt:.1f} s single-threaded",
+                  f"n=2^30, N=2^48, seed=7 sample: {dtn:.2f} s on {threads} threads "
+                  f"(consecutive sub-windows), {dt1:.1f} s on one thread",
+        "single_thread": {"value": count / dt1, "unit": "samples/s", "cores": 1},
+        "threads_match_single": same,
+        "host": host_description(),
         "matches_gpu": bool(np.array_equal(got, want)),
     }
 

@@ -20,8 +20,10 @@
  *   - Output values are 1-based (elements of 1..N) as uint64, ascending.
  *   - Return value: a dcs_status code.  Device-side failures (a capacity
  *     bound exceeded inside a kernel) cannot be returned by an asynchronous
- *     call; they are latched in a device error word and reported by
- *     dcs_synchronize() on that stream.
+ *     call; they are latched in an error word that the library owns, one per
+ *     stream (per device), and reported by dcs_synchronize() on that stream.
+ *     A caller workspace is only touched by the call it is passed to: the
+ *     library keeps no pointer to it afterwards.
  *   - The sample is a pure function of (variant, n or p, N, seed, n0,
  *     dense_ratio): launch geometry, batch composition and arrival order never
  *     change a bit of it (paper Sec. 4.5, strengthened: no dependence on the
@@ -235,6 +237,10 @@ uint64_t dcs_batch_total(const dcs_batch* batch);
  *     larger than the arena.
  *   dcs_server_submit_schedule: a host thread submits requests[i] at time
  *     arrival_s[i] (open loop); returns at once.  The arrays are copied.
+ *     Request i gets ticket *first_ticket + i, reserved before the call
+ *     returns (it polls as queued until it arrives).  DCS_EINVAL, with
+ *     nothing submitted, if any request fails dcs_server_submit's checks or
+ *     another schedule is still being fed.
  *   dcs_server_poll: state 0 queued, 1 running, 2 done; out_dev (valid once
  *     done, until released) and latency_s (done only) may be NULL.
  *   dcs_server_release: frees a done request's arena space.
@@ -276,8 +282,12 @@ int32_t dcs_server_stats_read(dcs_server* server, dcs_server_stats* stats);
 int32_t dcs_server_destroy(dcs_server* server);
 double dcs_server_now(void);
 
-/* Waits for `stream`, then reports and clears any error latched by the
- * library's kernels: DCS_EDEVICE if one was latched, else DCS_OK. */
+/* Waits for `stream`, then reports and clears the errors latched by the
+ * library's kernels of calls enqueued on `stream` (on the current device)
+ * since the last dcs_synchronize of that stream: DCS_EDEVICE if one was
+ * latched, else DCS_OK.  Calls on other streams are neither waited for nor
+ * reported (the first 62 streams that launch work on a device have words of
+ * their own; later ones share one word). */
 int32_t dcs_synchronize(void* stream);
 
 /*

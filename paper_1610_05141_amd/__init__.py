@@ -255,7 +255,7 @@ def bernoulli_capacity_hint(p: float, N: int) -> int:
 
 
 def sample_bernoulli(p: float, N: int, seed: int, out=None, capacity=None, count=None,
-                     stream=None, n0=None):
+                     stream=None, n0=None, workspace=None):
     """Bernoulli(p) sample of 1..N.  Returns (out, count) tensors; count is a
     1-element int64 CUDA tensor with the true number of hits."""
     import torch
@@ -264,8 +264,10 @@ def sample_bernoulli(p: float, N: int, seed: int, out=None, capacity=None, count
     out = _out_tensor(out, capacity)
     if count is None:
         count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws, wsb = (_ptr(workspace), workspace.numel() * workspace.element_size()) \
+        if workspace is not None else (ctypes.c_void_p(0), 0)
     rc = lib().dcs_sample_bernoulli_ex(float(p), N, seed, _params(n0, None), _ptr(out), capacity,
-                                       _ptr(count), ctypes.c_void_p(0), 0, _stream_handle(stream))
+                                       _ptr(count), ws, wsb, _stream_handle(stream))
     _check(rc, "dcs_sample_bernoulli_ex")
     return out, count
 

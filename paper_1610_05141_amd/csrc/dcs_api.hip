@@ -10,8 +10,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
-#include <set>
 #include <vector>
 
 #include "../../include/dcs.h"
@@ -183,7 +183,6 @@ double host_log1p_series(double x) {
 
 std::mutex g_mu;
 std::vector<DeviceCtx> g_dev;
-std::set<void*> g_ctl_used;  // control blocks to check at synchronize
 bool g_profile = false;
 std::vector<Timing> g_timings;
 uint32_t g_prof_mask = ~0u;                        // kinds that are timed
@@ -230,11 +229,25 @@ int32_t device_ctx(DeviceCtx** out) {
     c.bern_wave_occupancy = dcs::bern_wave_occupancy();
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
-
+    if (dcs::error_slots(&c.err_slots) != hipSuccess || c.err_slots == nullptr) return DCS_EHIP;
     c.init = true;
   }
   *out = &c;
   return DCS_OK;
+}
+
+unsigned int* error_word(DeviceCtx* c, void* stream) {
+  auto it = c->err_slot_of.find(stream);
+  if (it != c->err_slot_of.end()) return c->err_slots + it->second;
+  // slot 0: the null stream; 1 .. kErrSlots-2: other streams in order of
+  // first use; kErrSlots-1: shared by every stream after those
+  int slot = 0;
+  if (stream != nullptr) {
+    const int used = static_cast<int>(c->err_slot_of.size() - c->err_slot_of.count(nullptr));
+    slot = std::min(1 + used, dcs::kErrSlots - 1);
+  }
+  c->err_slot_of[stream] = slot;
+  return c->err_slots + slot;
 }
 
 // ---- tuning table ------------------------------------------------------------
@@ -260,14 +273,12 @@ int32_t own_workspace(DeviceCtx* c, size_t bytes, void** ws) {
   if (c->ws_bytes < bytes) {
     if (c->ws) {
       if (hipDeviceSynchronize() != hipSuccess) return DCS_EHIP;
-      g_ctl_used.erase(c->ws);
       if (hipFree(c->ws) != hipSuccess) return DCS_EHIP;
       c->ws = nullptr;
       c->ws_bytes = 0;
     }
     size_t grow = std::max(bytes, static_cast<size_t>(64) << 20);
     if (hipMalloc(&c->ws, grow) != hipSuccess) return DCS_ENOMEM;
-    if (hipMemset(c->ws, 0, sizeof(Control)) != hipSuccess) return DCS_EHIP;
     c->ws_bytes = grow;
   }
   *ws = c->ws;
@@ -300,7 +311,7 @@ void timing_end(hipStream_t s, Timing* t) {
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors, uint32_t leaf_wgs_per_cu, uint64_t* part_out) {
+                          unsigned int* err, uint32_t leaf_wgs_per_cu, uint64_t* part_out) {
   if (leaf_cap >= dcs::kMaxLeafJobs) return DCS_ENOMEM;
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
@@ -310,7 +321,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   Node* frontier = reinterpret_cast<Node*>(base + L.frontier);
   Timing t0{}, t1{}, t2{};
   timing_begin(0, s, &t0);
-  hipError_t e = dcs::launch_reset(ctl, single, inst, s);
+  hipError_t e = dcs::launch_reset(ctl, single, inst, err, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   timing_begin(1, s, &t1);
@@ -345,7 +356,6 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   }
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
-  if (register_errors) g_ctl_used.insert(ctl);
   return DCS_OK;
 }
 
@@ -386,8 +396,8 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   I.cut = pl.cut;
   I.top_cut = pl.top_cut;
   return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.top_threads, pl.leaf_cap,
-                           pl.stack_depth, out, static_cast<hipStream_t>(stream), true,
-                           leaf_wgs_for(c, variant, n));
+                           pl.stack_depth, out, static_cast<hipStream_t>(stream),
+                           error_word(c, stream), leaf_wgs_for(c, variant, n));
 }
 
 struct BernLayout {
@@ -481,7 +491,8 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
   I.part = index;
   I.part_cap = capacity;
   return run_tree_pipeline(c, ws, L, &I, 1, pl.threads, pl.top_threads, pl.leaf_cap,
-                           pl.stack_depth, out_dev, static_cast<hipStream_t>(stream), true,
+                           pl.stack_depth, out_dev, static_cast<hipStream_t>(stream),
+                           error_word(c, stream),
                            leaf_wgs_for(c, static_cast<uint32_t>(variant), np), count_rank_dev);
 }
 
@@ -529,7 +540,7 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
   const int fp32 = p >= 0x1p-10 ? 1 : 0;
   Timing t0{}, t1{};
   timing_begin(0, s, &t0);
-  hipError_t e = dcs::launch_zero(ctl, status, n_chunks, tickets, s);
+  hipError_t e = dcs::launch_zero(ctl, status, n_chunks, tickets, error_word(c, stream), s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   // LDS offsets per double-precision chunk: 2 n0 + 64, or fewer when a full
@@ -553,7 +564,6 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
                             count_dev, ctl, tickets, grid, lds_cap, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
-  g_ctl_used.insert(ctl);
   return DCS_OK;
 }
 
@@ -675,13 +685,16 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
   const uint32_t n_inst = static_cast<uint32_t>(b->host.size());
+  unsigned int* err = error_word(c, stream);
   if (!use_graph || g_profile) {
     return run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
-                             b->leaf_cap, b->stack_depth, out_dev, s, true,
+                             b->leaf_cap, b->stack_depth, out_dev, s, err,
                              leaf_wgs_for(c, 0, b->total_out));
   }
   if (s == nullptr) return DCS_EINVAL;  // capture needs a real stream
-  if (b->exec == nullptr || b->graph_out != out_dev) {
+  // the captured reset names the output and the stream's error word:
+  // capture again when either changes
+  if (b->exec == nullptr || b->graph_out != out_dev || b->graph_stream != s) {
     if (b->exec) {
       (void)hipGraphExecDestroy(b->exec);
       b->exec = nullptr;
@@ -692,7 +705,7 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DCS_EHIP;
     rc = run_tree_pipeline(c, b->ws, b->layout, nullptr, n_inst, b->threads, b->top_threads,
-                           b->leaf_cap, b->stack_depth, out_dev, s, true,
+                           b->leaf_cap, b->stack_depth, out_dev, s, err,
                            leaf_wgs_for(c, 0, b->total_out));
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
@@ -701,6 +714,7 @@ int32_t dcs_batch_run(dcs_batch* b, uint64_t* out_dev, int32_t use_graph, void* 
     b->graph = g;
     if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return DCS_EHIP;
     b->graph_out = out_dev;
+    b->graph_stream = s;
   }
   return hip_status(hipGraphLaunch(b->exec, s));
 }
@@ -711,8 +725,6 @@ int32_t dcs_batch_destroy(dcs_batch* b) {
   (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  char* base = static_cast<char*>(b->ws);
-  g_ctl_used.erase(base + b->layout.ctl);
   if (b->ws) (void)hipFree(b->ws);
   delete b;
   return DCS_OK;
@@ -720,19 +732,22 @@ int32_t dcs_batch_destroy(dcs_batch* b) {
 
 // ---- status, timing, diagnostics -------------------------------------------
 int32_t dcs_synchronize(void* stream) {
-  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DCS_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(s) != hipSuccess) return DCS_EHIP;
   std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  // this stream's error word: everything its calls latched since the last
+  // synchronize (read and cleared in stream order, after the stream's work)
+  unsigned int* word = error_word(c, stream);
   unsigned int any = 0;
-  for (void* p : g_ctl_used) {
-    Control* ctl = static_cast<Control*>(p);
-    unsigned int err = 0;
-    if (hipMemcpy(&err, &ctl->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return DCS_EHIP;
-    if (err) {
-      any |= err;
-      const unsigned int zero = 0;
-      if (hipMemcpy(&ctl->error, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return DCS_EHIP;
-    }
-  }
+  if (hipMemcpyAsync(&any, word, sizeof(any), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DCS_EHIP;
+  if (any != 0 && (hipMemsetAsync(word, 0, sizeof(unsigned int), s) != hipSuccess ||
+                   hipStreamSynchronize(s) != hipSuccess))
+    return DCS_EHIP;
   if (g_profile) {
     for (Timing& t : g_timings) {
       float ms = 0;

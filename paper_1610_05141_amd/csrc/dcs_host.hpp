@@ -6,8 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
-#include <set>
 
 #include "../../include/dcs.h"
 #include "dcs_kernels.hpp"
@@ -53,7 +53,16 @@ struct DeviceCtx {
   int64_t leaf_grid = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // the library's error words on this device (kErrSlots of them) and the
+  // stream each one serves; slot 0 is the null stream's, the last one is
+  // shared by streams beyond the others
+  unsigned int* err_slots = nullptr;
+  std::map<void*, int> err_slot_of;
 };
+
+// Error word of `stream` on the current device (assigned on first use);
+// caller holds lock().
+unsigned int* error_word(DeviceCtx* c, void* stream);
 
 // Tuned launch geometry of a size class (variant, floor(log2 n)), set through
 // dcs_tune_set; never changes a sample.
@@ -77,13 +86,15 @@ std::mutex& lock();
 // Context of the current device (creates it on first use); caller holds lock().
 int32_t device_ctx(DeviceCtx** out);
 // Enqueue reset + tree + leaf on `s` for the instances in the workspace
-// (`single` != NULL: store that one instance first); caller holds lock().
+// (`single` != NULL: store that one instance first); the kernels latch
+// errors at `err` (nullptr: the workspace's own control block); caller
+// holds lock().
 // Leaf work-groups: DCS_LEAF_GRID if set, else cus * leaf_wgs_per_cu (both
 // leaf kernels use it).
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          bool register_errors, uint32_t leaf_wgs_per_cu,
+                          unsigned int* err, uint32_t leaf_wgs_per_cu,
                           uint64_t* part_out = nullptr);
 
 // Kernel timing with pooled HIP events on the launch stream (dcs_profile_*):

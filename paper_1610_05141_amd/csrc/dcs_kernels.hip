@@ -1101,7 +1101,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
   if (front + back > leaf_cap) {
     // the lists overlap (or one overflowed): the tree kernel flagged or
     // would have flagged capacity; report it and sample nothing
-    if (!kPow2 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->error, kErrLeafCapacity);
+    if (!kPow2 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(ctl->err, kErrLeafCapacity);
     return;
   }
   const uint64_t n_leaves = kPow2 ? front : back;
@@ -1265,7 +1265,7 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
   const uint64_t base = front ? (old & 0xFFFFFFFFull) : (old >> 32);
   for (uint64_t j = 0; j < pieces; ++j) {
     if (base + j >= cap) {
-      atomicOr(&ctl->error, kErrLeafCapacity);
+      atomicOr(ctl->err, kErrLeafCapacity);
       return;
     }
     const uint64_t at = front ? base + j : cap - 1 - (base + j);
@@ -1416,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
       const Node right{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
       if (right.nv > 0) {
         if (sp == stack_depth) {
-          atomicOr(&ctl->error, kErrStackDepth);
+          atomicOr(ctl->err, kErrStackDepth);
           return;
         }
         stk[sp++] = right;
@@ -1428,24 +1428,28 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
   }
 }
 
-__global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table) {
+__device__ inline void start_control(Control* ctl, unsigned int* err) {
+  ctl->leaf_counts = 0;
+  ctl->bern_count = 0;
+  ctl->error = 0;
+  ctl->err = err != nullptr ? err : &ctl->error;
+}
+
+__global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table,
+                        unsigned int* err) {
   if (threadIdx.x == 0) {
-    ctl->leaf_counts = 0;
-    ctl->bern_count = 0;
+    start_control(ctl, err);
     if (has_single) table[0] = single;
   }
 }
 
 __global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n,
-                       unsigned long long* tickets) {
+                       unsigned long long* tickets, unsigned int* err) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     status[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x < kTicketWords) tickets[threadIdx.x] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->leaf_counts = 0;
-    ctl->bern_count = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) start_control(ctl, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1554,7 +1558,7 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
     const unsigned long long upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
     if (none & upto) {
       if (++spins > kSpinLimit) {
-        if (lane == 0) atomicOr(&ctl->error, kErrSpinLimit);
+        if (lane == 0) atomicOr(ctl->err, kErrSpinLimit);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
@@ -1825,20 +1829,28 @@ __global__ void k_debug(int op, const void* x, const void* x2, void* y, uint64_t
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, hipStream_t stream) {
+// The library's error words (zero at load; see error_slots).
+static __device__ unsigned int g_err_slots[kErrSlots];
+
+hipError_t error_slots(unsigned int** out) {
+  return hipGetSymbolAddress(reinterpret_cast<void**>(out), HIP_SYMBOL(g_err_slots));
+}
+
+hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
+                        hipStream_t stream) {
   Instance one{};
   if (single) one = *single;
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctl, one, single ? 1 : 0, table);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctl, one, single ? 1 : 0, table, err);
   return hipGetLastError();
 }
 
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
-                       unsigned long long* tickets, hipStream_t stream) {
+                       unsigned long long* tickets, unsigned int* err, hipStream_t stream) {
   uint64_t blocks = (n + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_zero, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, status, n,
-                     tickets);
+                     tickets, err);
   return hipGetLastError();
 }
 

@@ -60,12 +60,25 @@ struct Control {
   // high 32 bits all others (filled from the back); one 64-bit atomic
   // serves both
   unsigned long long leaf_counts;
-  unsigned long long pad0;
+  // where the kernels latch error bits (kErr*): a library-owned word of the
+  // launch stream, or `error` below when the caller reads the block itself
+  // (the serving loop); set by k_reset / k_zero at the start of every call
+  unsigned int* err;
   unsigned long long pad1;
-  unsigned int error;              // latched error bits (kErr*)
+  unsigned int error;              // this call's own error bits (see `err`)
   unsigned int pad;
   unsigned long long bern_count;   // Bernoulli: total hits (copied to the caller)
 };
+static_assert(sizeof(Control) == 40, "control block layout");
+
+// Library-owned error words, one per stream that has launched work (the
+// last one shared by streams beyond kErrSlots - 1), per device: kept in
+// device memory the library owns, so that nothing outside a call's own
+// buffers is ever written after the call, and read and cleared by
+// dcs_synchronize for its stream only.
+constexpr int kErrSlots = 64;
+// Device address of this device's error words (call with the device current).
+hipError_t error_slots(unsigned int** out);
 
 constexpr unsigned kErrLeafCapacity = 1u;   // more leaves than the workspace holds
 constexpr unsigned kErrStackDepth = 2u;     // tree deeper than the planned stack
@@ -84,14 +97,16 @@ constexpr uint32_t kTicketStride = 32;
 constexpr uint32_t kTicketWords = kTicketClasses * kTicketStride;
 
 // Kernel launchers (defined in dcs_kernels.hip).
-// Zero the counters of a control block (the error word is kept: it is
-// sticky until the host reads and clears it); if `single` is non-null, also
-// store that instance as entry 0 of the instance table.
-hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, hipStream_t stream);
+// Start a call on a control block: zero its counters and its own error word
+// and point its kernels' error latch at `err` (nullptr: at the block's own
+// error word); if `single` is non-null, also store that instance as entry 0
+// of the instance table.
+hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
+                        hipStream_t stream);
 // launch_reset for a Bernoulli call plus zeroing of its look-back status words
 // and its kTicketWords chunk counters.
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
-                       unsigned long long* tickets, hipStream_t stream);
+                       unsigned long long* tickets, unsigned int* err, hipStream_t stream);
 // Resident leaf work-groups per compute unit.
 int leaf_occupancy();
 // Resident k_leaf_dense work-groups (one wave each) per compute unit.

@@ -46,6 +46,7 @@ struct Req {
   uint64_t off = 0, bytes = 0;  // arena placement
   int state = 0;                // 0 queued, 1 running, 2 done
   bool released = false;
+  bool arrived = false;         // in the admission queue (scheduled ones: from arrival)
 };
 
 struct Slot {
@@ -248,7 +249,7 @@ bool dcs_server::launch_batch() {
   }
   int32_t rc = dcs::host::run_tree_pipeline(c, sl->ws, L, nullptr, n_inst, threads, top_threads,
                                             leaf_cap, stack_depth,
-                                            reinterpret_cast<uint64_t*>(arena), sl->stream, false,
+                                            reinterpret_cast<uint64_t*>(arena), sl->stream, nullptr,
                                             dcs::host::leaf_wgs_for(c, 0, total_n));
   if (rc == DCS_OK &&
       (hipMemcpyAsync(sl->err, &reinterpret_cast<Control*>(base + L.ctl)->error,
@@ -318,20 +319,36 @@ int32_t dcs_server_create(uint64_t arena_bytes, uint32_t max_batch, uint32_t n_s
   return DCS_OK;
 }
 
-static int32_t submit_locked(dcs_server* s, const dcs_request* r, double arrival, uint64_t* ticket) {
+// Output footprint of a request in the arena (8 n bytes, 256-byte granules).
+static uint64_t footprint(const dcs_request* r) { return (r->n * 8 + 255) / 256 * 256; }
+
+// The one acceptance rule for every way a request enters the server.
+static bool request_ok(const dcs_server* s, const dcs_request* r) {
   if (r->variant > 1 || r->N > DCS_MAX_UNIVERSE || (r->variant == 0 && r->n > r->N) ||
       (r->variant == 1 && r->N == 0 && r->n > 0) || (r->n0 != 0 && (r->n0 < 2 || r->n0 > 4096)))
-    return DCS_EINVAL;
-  const uint64_t bytes = (r->n * 8 + 255) / 256 * 256;
-  if (bytes > s->arena_bytes) return DCS_EINVAL;
+    return false;
+  // n <= N <= 2^52 (or n of a with-replacement request below 2^60): no overflow
+  if (r->n > (1ull << 60)) return false;
+  return footprint(r) <= s->arena_bytes;
+}
+
+// Enters ticket `tk` (already in reqs) into the admission queue.
+static void arrive_locked(dcs_server* s, uint64_t tk) {
+  Req& R = s->reqs[tk];
+  R.arrived = true;
+  s->pending.push_back(tk);
+  s->first_arrival = std::min(s->first_arrival, R.arrival);
+}
+
+static int32_t submit_locked(dcs_server* s, const dcs_request* r, double arrival, uint64_t* ticket) {
+  if (!request_ok(s, r)) return DCS_EINVAL;
   Req R;
   R.r = *r;
   R.arrival = arrival < 0 ? now_s() : arrival;
-  R.bytes = bytes;
+  R.bytes = footprint(r);
   const uint64_t tk = s->reqs.size();
   s->reqs.push_back(R);
-  s->pending.push_back(tk);
-  s->first_arrival = std::min(s->first_arrival, R.arrival);
+  arrive_locked(s, tk);
   if (ticket) *ticket = tk;
   return DCS_OK;
 }
@@ -350,22 +367,29 @@ int32_t dcs_server_submit(dcs_server* s, const dcs_request* r, double arrival_s,
 int32_t dcs_server_submit_schedule(dcs_server* s, const dcs_request* requests,
                                    const double* arrival_s, uint64_t count, uint64_t* first_ticket) {
   if (s == nullptr || (count > 0 && (requests == nullptr || arrival_s == nullptr))) return DCS_EINVAL;
-  std::vector<dcs_request> rq(requests, requests + count);
   std::vector<double> at(arrival_s, arrival_s + count);
+  uint64_t first = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->feeding) return DCS_EINVAL;  // one schedule at a time
-    for (const dcs_request& r : rq) {
-      if (r.variant > 1 || r.N > DCS_MAX_UNIVERSE || (r.variant == 0 && r.n > r.N) ||
-          (r.n * 8 + 255) / 256 * 256 > s->arena_bytes)
-        return DCS_EINVAL;
+    for (uint64_t i = 0; i < count; ++i)
+      if (!request_ok(s, &requests[i])) return DCS_EINVAL;
+    // every request's ticket is reserved now (first + i), so that tickets
+    // from concurrent dcs_server_submit calls come after the schedule's
+    first = s->reqs.size();
+    for (uint64_t i = 0; i < count; ++i) {
+      Req R;
+      R.r = requests[i];
+      R.arrival = at[i];
+      R.bytes = footprint(&requests[i]);
+      s->reqs.push_back(R);
     }
-    if (first_ticket) *first_ticket = s->reqs.size();
+    if (first_ticket) *first_ticket = first;
     s->feeding = true;
   }
   if (s->feeder.joinable()) s->feeder.join();
-  s->feeder = std::thread([s, rq = std::move(rq), at = std::move(at)] {
-    for (size_t i = 0; i < rq.size(); ++i) {
+  s->feeder = std::thread([s, first, at = std::move(at)] {
+    for (size_t i = 0; i < at.size(); ++i) {
       for (;;) {
         const double d = at[i] - now_s();
         if (d <= 0) break;
@@ -374,7 +398,7 @@ int32_t dcs_server_submit_schedule(dcs_server* s, const dcs_request* requests,
       }
       {
         std::lock_guard<std::mutex> lk(s->mu);
-        submit_locked(s, &rq[i], at[i], nullptr);
+        arrive_locked(s, first + i);
       }
       s->cv.notify_all();
     }

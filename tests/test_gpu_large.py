@@ -63,6 +63,10 @@ def test_config2b_dense_4gib(ref):
 
 
 def test_config3a_bernoulli(ref):
+    """The whole p = 0.01 sample of 1..2^36 and its count against the
+    oracle, which recomputes it in blocks of chunks on several host threads
+    (each block is independent: Sec. 4.7's subranges)."""
+    from concurrent.futures import ThreadPoolExecutor
     p, N, seed = 0.01, 1 << 36, 7
     m = dcs()
     announce("config 3a Bernoulli full size")
@@ -75,15 +79,19 @@ def test_config3a_bernoulli(ref):
     assert _strictly_increasing(out, 1, N)
     C = ref.bernoulli_chunk_len(p)
     n_chunks = (N + C - 1) // C
-    rng = np.random.default_rng(3)
-    import torch
-    for j in [0, n_chunks - 4] + [int(x) for x in rng.integers(0, n_chunks - 4, 12)]:
-        want = ref.bernoulli_chunks(p, N, seed, j, j + 4)
-        lo = int(torch.searchsorted(out, torch.tensor([j * C + 1], device="cuda")).item())
-        got = to_np_u64(out[lo:lo + want.size])
-        assert np.array_equal(got, want), f"chunks {j}..{j + 3}: {first_mismatch(got, want)}"
-        if lo + want.size < c:
-            assert int(out[lo + want.size]) > (j + 4) * C
+    per = 4096  # chunks per block: ~1.07e7 hits
+    blocks = [(j, min(n_chunks, j + per)) for j in range(0, n_chunks, per)]
+    cap = int(per * C * p + 12 * math.sqrt(per * C * p) + 64)
+    announce(f"config 3a: oracle over all {n_chunks} chunks in {len(blocks)} blocks")
+    pos = 0
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for (j0, j1), want in zip(blocks, ex.map(
+                lambda b: ref.bernoulli_chunks(p, N, seed, b[0], b[1], capacity=cap), blocks)):
+            assert want.size < cap
+            got = to_np_u64(out[pos:pos + want.size])
+            assert np.array_equal(got, want), f"chunks {j0}..{j1 - 1}: {first_mismatch(got, want)}"
+            pos += want.size
+    assert pos == c, f"oracle count {pos} != GPU count {c}"
 
 
 def test_config3b_with_replacement(ref):

@@ -66,3 +66,35 @@ def test_server_admission_under_pressure():
         time.sleep(0.001)
     assert not pending, f"{len(pending)} requests never completed"
     srv.close()
+
+
+def test_schedule_rejects_invalid_request_and_keeps_tickets():
+    """A schedule with an invalid request (n0 above 4096) is refused whole;
+    a valid schedule's request i has ticket first + i even when plain
+    submissions arrive while it is being fed."""
+    import torch
+    m = dcs()
+    announce("server schedule validation and ticket order")
+    srv = m.Server(arena_bytes=1 << 28, max_batch=16, n_streams=2, auto_release=False)
+    bad = [(1000, 1 << 30, 1), (1000, 1 << 30, 2, 0, 5000), (1000, 1 << 30, 3)]
+    t0 = m.Server.now()
+    with pytest.raises(m.DcsError):
+        srv.submit_schedule(bad, [t0, t0, t0])
+    reqs = [(500 + 37 * i, 1 << 34, 100 + i) for i in range(40)]
+    arrivals = [m.Server.now() + 0.002 * i for i in range(len(reqs))]
+    first = srv.submit_schedule(reqs, arrivals)
+    extra = [srv.submit(777, 1 << 20, 5000 + k) for k in range(5)]
+    assert all(t >= first + len(reqs) for t in extra)
+    srv.drain()
+    assert srv.stats()["completed"] == len(reqs) + len(extra)
+    for i, (n, N, s) in enumerate(reqs):
+        got = srv.result(first + i, n)
+        alone = m.sample(n, N, s)
+        m.synchronize()
+        assert torch.equal(got, alone), f"ticket {first + i} is not request {i}"
+    for k, tk in enumerate(extra):
+        got = srv.result(tk, 777)
+        alone = m.sample(777, 1 << 20, 5000 + k)
+        m.synchronize()
+        assert torch.equal(got, alone)
+    srv.close()
