@@ -82,6 +82,27 @@ int32_t dcs_sample_ex(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* p
                       uint64_t* out_dev, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * dcs_sample_noalloc -- dcs_sample_ex without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, same
+ * sample bit for bit as dcs_sample_ex(n, N, seed, params, out_dev, ...).
+ * Its workspace is a static device array of DCS_NOALLOC_SCRATCH_BYTES per
+ * device, created when the library is loaded and held until the process
+ * ends; the call makes no hipMalloc / hipFree and no allocating library
+ * call.  Every call on a device shares that device's array (each call
+ * clears what must start at zero), so calls on one device that overlap in
+ * time race: enqueue them on one stream, or wait for one before the next.
+ * Errors: those of dcs_sample_ex, and DCS_ENOMEM (nothing enqueued) when
+ * the call needs more than DCS_NOALLOC_SCRATCH_BYTES, i.e. when
+ * dcs_workspace_size(0, n, N, 0, params) exceeds it (with the committed
+ * tuning table n = 2^28 of N = 2^40 needs about 47 MiB and fits, while any
+ * n from 2^25 up at N = 2^48 needs over 200 MiB and does not).
+ */
+#define DCS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t dcs_sample_noalloc(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                           uint64_t* out_dev, void* stream);
+
+/*
  * dcs_sample_replacement -- n integers drawn independently and uniformly
  * from 1..N, sorted non-decreasing, repeats kept (Sec. 4.6: Algorithm R with
  * a binomial instead of a hypergeometric split).

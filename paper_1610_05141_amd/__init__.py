@@ -13,7 +13,7 @@ import os
 from dataclasses import dataclass
 
 __all__ = [
-    "DcsError", "lib", "sample", "sample_replacement", "sample_bernoulli", "sample_part",
+    "DcsError", "lib", "sample", "sample_noalloc", "sample_replacement", "sample_bernoulli", "sample_part",
     "sample_edges_gnm", "sample_edges_gnp",
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
@@ -25,10 +25,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libdcs.so")
 
 DCS_OK, DCS_EINVAL, DCS_ENOMEM, DCS_EHIP, DCS_EOVERFLOW, DCS_EDEVICE, DCS_ENOTSUP = range(7)
+# Static scratch of dcs_sample_noalloc per device (DCS_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Every symbol declared in include/dcs.h.
 EXPORTED_SYMBOLS = (
-    "dcs_sample", "dcs_sample_ex", "dcs_sample_replacement", "dcs_sample_replacement_ex",
+    "dcs_sample", "dcs_sample_ex", "dcs_sample_noalloc", "dcs_sample_replacement", "dcs_sample_replacement_ex",
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
     "dcs_sample_part", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
@@ -88,6 +90,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "dcs_sample": (i32, [u64, u64, u64, vp, vp]),
             "dcs_sample_ex": (i32, [u64, u64, u64, pp, vp, vp, ctypes.c_size_t, vp]),
+            "dcs_sample_noalloc": (i32, [u64, u64, u64, pp, vp, vp]),
             "dcs_sample_replacement": (i32, [u64, u64, u64, vp, vp]),
             "dcs_sample_replacement_ex": (i32, [u64, u64, u64, pp, vp, vp, ctypes.c_size_t, vp]),
             "dcs_sample_bernoulli": (i32, [dbl, u64, u64, vp, u64, vp, vp]),
@@ -178,6 +181,17 @@ def sample(n: int, N: int, seed: int, out=None, stream=None, n0=None, dense_rati
     rc = lib().dcs_sample_ex(n, N, seed, _params(n0, dense_ratio), _ptr(out), ws, wsb,
                              _stream_handle(stream))
     _check(rc, "dcs_sample_ex")
+    return out
+
+
+def sample_noalloc(n: int, N: int, seed: int, out, stream=None, n0=None, dense_ratio=None):
+    """As sample(), into a caller tensor, with the library's static scratch:
+    the call allocates no device memory (DcsError DCS_ENOMEM if the sample
+    needs more than NOALLOC_SCRATCH_BYTES of workspace)."""
+    out = _out_tensor(out, n)
+    rc = lib().dcs_sample_noalloc(n, N, seed, _params(n0, dense_ratio), _ptr(out),
+                                  _stream_handle(stream))
+    _check(rc, "dcs_sample_noalloc")
     return out
 
 

@@ -35,6 +35,13 @@ constexpr uint64_t kLeafRange = 1ull << 32;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace of dcs_sample_noalloc: one copy of this array per device, held
+// from the library's load until the process ends.  Host code never passes
+// its name to a kernel (on the host it is only a stand-in for the symbol):
+// device_ctx looks up each device's address once with hipGetSymbolAddress,
+// and calls use that address.
+static __device__ __align__(256) unsigned char scratch[DCS_NOALLOC_SCRATCH_BYTES];
+
 uint32_t floor_log2(uint64_t x) { return x == 0 ? 0 : 63u - static_cast<uint32_t>(__builtin_clzll(x)); }
 
 uint64_t ceil_div_pow2(uint64_t N, uint32_t d) {
@@ -230,6 +237,9 @@ int32_t device_ctx(DeviceCtx** out) {
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
     if (dcs::error_slots(&c.err_slots) != hipSuccess || c.err_slots == nullptr) return DCS_EHIP;
+    if (hipGetSymbolAddress(&c.noalloc_scratch, HIP_SYMBOL(scratch)) != hipSuccess ||
+        c.noalloc_scratch == nullptr)
+      return DCS_EHIP;
     c.init = true;
   }
   *out = &c;
@@ -361,8 +371,11 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
 
 std::mutex& lock() { return g_mu; }
 
+// noalloc: run in this device's static scratch array (DCS_ENOMEM if the
+// call needs more); the call then allocates no device memory.
 int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
-                    uint64_t* out, void* workspace, size_t ws_bytes, void* stream) {
+                    uint64_t* out, void* workspace, size_t ws_bytes, void* stream,
+                    bool noalloc = false) {
   Params P;
   if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
   if (N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
@@ -377,7 +390,10 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   const Plan pl = make_plan(n, N, P.n0, variant, cut_bias_for(variant, n));
   const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
   void* ws = workspace;
-  if (ws == nullptr) {
+  if (noalloc) {
+    if (L.total > DCS_NOALLOC_SCRATCH_BYTES) return DCS_ENOMEM;
+    ws = c->noalloc_scratch;
+  } else if (ws == nullptr) {
     rc = own_workspace(c, L.total, &ws);
     if (rc) return rc;
   } else if (ws_bytes < L.total) {
@@ -435,6 +451,11 @@ int32_t dcs_sample(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev, voi
 int32_t dcs_sample_ex(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
                       uint64_t* out_dev, void* workspace, size_t ws_bytes, void* stream) {
   return sample_tree(0, n, N, seed, params, out_dev, workspace, ws_bytes, stream);
+}
+
+int32_t dcs_sample_noalloc(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                           uint64_t* out_dev, void* stream) {
+  return sample_tree(0, n, N, seed, params, out_dev, nullptr, 0, stream, true);
 }
 
 int32_t dcs_sample_replacement(uint64_t n, uint64_t N, uint64_t seed, uint64_t* out_dev,

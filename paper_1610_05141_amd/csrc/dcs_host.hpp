@@ -53,6 +53,9 @@ struct DeviceCtx {
   int64_t leaf_grid = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device address of this device's copy of the allocation-free entry
+  // point's static scratch array (hipGetSymbolAddress at set-up)
+  void* noalloc_scratch = nullptr;
   // the library's error words on this device (kErrSlots of them) and the
   // stream each one serves; slot 0 is the null stream's, the last one is
   // shared by streams beyond the others
