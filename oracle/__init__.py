@@ -22,6 +22,7 @@ CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 # Stream purposes (same meaning as the library's; restated here on purpose).
 P_SPLIT, P_LEAF, P_BERN, P_REPAIR, P_BCHUNK, P_WRSPLIT, P_WRLEAF = 1, 2, 3, 4, 5, 6, 7
+P_SEGSPLIT, P_SEGSEED = 8, 9
 
 DEFAULT_N0 = 4096
 DEFAULT_DENSE_RATIO = 16
@@ -91,6 +92,8 @@ def configure(L: ctypes.CDLL) -> ctypes.CDLL:
             "dcs_ref_hyp_batch": (None, [u64, u64, u64, u64, u64, u64, p64]),
             "dcs_ref_bin_batch": (None, [u64, u64, u64, u64, u64, u64, p64]),
             "dcs_ref_range_map_counts": (None, [u64, p64, p64]),
+            "dcs_ref_segment_tree": (i32, [u64, p64, u64, u64, p64, p64]),
+            "dcs_ref_sample_segments": (i32, [u64, p64, u64, u64, u32, u32, p64, p64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -157,6 +160,36 @@ def part(variant: int, n: int, N: int, seed: int, depth: int, index: int,
         return None, count, r
     _check(rc, "part")
     return out[:count].copy(), count, r
+
+
+def _lengths(lengths) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(lengths, dtype=np.uint64))
+
+
+def segment_tree(n: int, lengths, seed: int) -> tuple:
+    """The two passes of Sec. 4.3 over the binomial tree of the segments:
+    (sums, counts), each indexed by heap id 1 .. 2^(D+1)-1 (entry 0 unused;
+    node (level j, subtree a) has id 2^(D-j) + a, D = ceil(log2 K))."""
+    L = _lengths(lengths)
+    D = max(0, (len(L) - 1).bit_length())
+    sums = np.zeros(2 << D, dtype=np.uint64)
+    cnt = np.zeros(2 << D, dtype=np.uint64)
+    _check(lib().dcs_ref_segment_tree(n, _p64(L), len(L), seed, _p64(sums), _p64(cnt)),
+           "segment_tree")
+    return sums, cnt
+
+
+def sample_segments(n: int, lengths, seed: int, n0: int = DEFAULT_N0,
+                    dense_ratio: int = DEFAULT_DENSE_RATIO) -> tuple:
+    """n distinct values of 1..sum(lengths), ascending, computed segment by
+    segment (Sec. 4.3, uneven universe): returns (values, per-segment
+    counts)."""
+    L = _lengths(lengths)
+    out = np.empty(max(n, 1), dtype=np.uint64)
+    counts = np.zeros(max(len(L), 1), dtype=np.uint64)
+    _check(lib().dcs_ref_sample_segments(n, _p64(L), len(L), seed, n0, dense_ratio, _p64(out),
+                                         _p64(counts)), "sample_segments")
+    return out[:n].copy(), counts[:len(L)].copy()
 
 
 def edge_pair(k: int) -> tuple:

@@ -66,7 +66,9 @@ enum {
   P_REPAIR = 4,  /* dense leaf: which Bernoulli hits to remove */
   P_BCHUNK = 5,  /* Bernoulli variant: geometric skips of one chunk */
   P_WRSPLIT = 6, /* binomial split of a with-replacement node */
-  P_WRLEAF = 7   /* with-replacement leaf: uniform offsets */
+  P_WRLEAF = 7,  /* with-replacement leaf: uniform offsets */
+  P_SEGSPLIT = 8, /* uneven universe: split of a subtree of segments */
+  P_SEGSEED = 9   /* uneven universe: the seed of one segment's own tree */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -391,12 +393,13 @@ static uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N, draws_t *dr) {
   }
 }
 
-/* Hyp(n, M, N) from the (seed, id, SPLIT) stream. */
-static uint64_t hyp(uint64_t n, uint64_t M, uint64_t N, uint64_t seed, uint64_t id) {
+/* Hyp(n, M, N) from the (seed, id, purpose) stream. */
+static uint64_t hyp_stream(uint64_t n, uint64_t M, uint64_t N, uint64_t seed, uint64_t id,
+                           uint32_t purpose) {
   if (n == 0 || M == 0) return 0;
   if (M == N) return n;
   if (n == N) return M;
-  draws_t dr = {make_stream(seed, id, P_SPLIT, 0), 0};
+  draws_t dr = {make_stream(seed, id, purpose, 0), 0};
   uint64_t n1 = n, M1 = M;
   int flip_n = 0, flip_m = 0;
   /* Sec. 2: for n > N/2 take the complement of the sample. */
@@ -407,6 +410,11 @@ static uint64_t hyp(uint64_t n, uint64_t M, uint64_t N, uint64_t seed, uint64_t 
   if (flip_m) k = n1 - k;
   if (flip_n) k = M - k;
   return k;
+}
+
+/* Hyp(n, M, N) of a tree split: the (seed, id, SPLIT) stream. */
+static uint64_t hyp(uint64_t n, uint64_t M, uint64_t N, uint64_t seed, uint64_t id) {
+  return hyp_stream(n, M, N, seed, id, P_SPLIT);
 }
 
 /* Binomial deviate Bin(n, l/Nv), 1 <= l <= Nv - l, from the (seed, id,
@@ -906,6 +914,121 @@ EXPORT int dcs_ref_bernoulli(double p, uint64_t N, uint64_t seed, uint32_t n0,
 
 EXPORT uint64_t dcs_ref_bernoulli_chunk_len(double p, uint32_t n0) {
   return bern_chunk(p, n0);
+}
+
+/* Sampling over an uneven universe (Sec. 4.3, owner computes).  The
+ * universe is the concatenation of K segments -- the paper's PEs 0..K-1,
+ * PE i holding L_i elements -- and the sample is n distinct elements of
+ * 1..N, N = L_0 + ... + L_{K-1}; segment i computes those that fall into
+ * it.
+ *
+ * The segments form the paper's binomial tree: at level j (level 0 = the
+ * segments) subtree a spans segments 2^j a .. min(2^j a + 2^j, K) - 1, and
+ * its children are subtrees 2a and 2a+1 of level j-1.  Upward pass: the
+ * element count of every subtree, level by level from j = 0.  Downward
+ * pass: the root (level D = ceil(log2 K)) holds n; an inner node holding n'
+ * gives its left subtree n_l = Hyp(n', L_l, L_l + L_r) and its right one
+ * n' - n_l.  The hash input of a node (Sec. 4.3: the range of PEs it
+ * represents) is its heap index 2^(D-j) + a, with the SEGSPLIT purpose; a
+ * node whose right subtree lies beyond K has L_r = 0, so n_l = n' (Hyp's
+ * exact case).
+ *
+ * Segment i then samples its n_i of L_i by Algorithm R (Fig. 1) keyed by
+ * seed_i = 64-bit draw 0 of (seed, 2^D + i, SEGSEED): the hash of its own
+ * leaf identity.  Its values are shifted by the elements of the segments
+ * before it and follow the samples of those segments. */
+#define REF_MAX_SEGMENTS (1ULL << 24)
+
+static uint32_t ceil_log2_u64(uint64_t k) {
+  uint32_t d = 0;
+  while ((1ULL << d) < k) ++d;
+  return d;
+}
+
+/* Both passes; sums[id] and cnt[id] for heap ids 1 .. 2^(D+1) - 1 (zeroed
+ * by the caller; subtrees that start at or beyond K keep 0). */
+static void segment_tree(uint64_t n, const uint64_t *L, uint64_t K, uint64_t seed, uint32_t D,
+                         uint64_t *sums, uint64_t *cnt) {
+  for (uint64_t a = 0; a < K; ++a) sums[(1ULL << D) + a] = L[a];
+  for (uint32_t j = 1; j <= D; ++j) {
+    uint64_t first = 1ULL << (D - j);
+    uint64_t width = (K + (1ULL << j) - 1) >> j;
+    for (uint64_t a = 0; a < width; ++a)
+      sums[first + a] = sums[2 * (first + a)] + sums[2 * (first + a) + 1];
+  }
+  cnt[1] = n;
+  for (uint32_t j = D; j >= 1; --j) {
+    uint64_t first = 1ULL << (D - j);
+    uint64_t width = (K + (1ULL << j) - 1) >> j;
+    for (uint64_t a = 0; a < width; ++a) {
+      uint64_t id = first + a;
+      uint64_t Ll = sums[2 * id], Lr = sums[2 * id + 1];
+      uint64_t nl = hyp_stream(cnt[id], Ll, Ll + Lr, seed, id, P_SEGSPLIT);
+      cnt[2 * id] = nl;
+      cnt[2 * id + 1] = cnt[id] - nl;
+    }
+  }
+}
+
+static int segments_check(uint64_t n, const uint64_t *lengths, uint64_t K, uint64_t *N) {
+  if (K == 0 || K > REF_MAX_SEGMENTS || lengths == NULL) return REF_EINVAL;
+  uint64_t total = 0;
+  for (uint64_t i = 0; i < K; ++i) {
+    if (lengths[i] > REF_MAX_N - total) return REF_EINVAL;
+    total += lengths[i];
+  }
+  if (n > total) return REF_EINVAL;
+  *N = total;
+  return REF_OK;
+}
+
+/* The two passes alone: sums and cnt receive 2^(D+1) entries each (entry 0
+ * unused), in heap order. */
+EXPORT int dcs_ref_segment_tree(uint64_t n, const uint64_t *lengths, uint64_t K, uint64_t seed,
+                                uint64_t *sums, uint64_t *cnt) {
+  uint64_t N;
+  if (segments_check(n, lengths, K, &N) != REF_OK || sums == NULL || cnt == NULL)
+    return REF_EINVAL;
+  uint32_t D = ceil_log2_u64(K);
+  memset(sums, 0, (2ULL << D) * sizeof(uint64_t));
+  memset(cnt, 0, (2ULL << D) * sizeof(uint64_t));
+  segment_tree(n, lengths, K, seed, D, sums, cnt);
+  return REF_OK;
+}
+
+/* The sample: out[0..n) ascending (values in 1..N); counts[i] = n_i if
+ * counts is not NULL. */
+EXPORT int dcs_ref_sample_segments(uint64_t n, const uint64_t *lengths, uint64_t K,
+                                   uint64_t seed, uint32_t n0, uint32_t dense_ratio,
+                                   uint64_t *out, uint64_t *counts) {
+  uint64_t N;
+  if (check_params(n0, dense_ratio) != REF_OK) return REF_EINVAL;
+  if (segments_check(n, lengths, K, &N) != REF_OK) return REF_EINVAL;
+  if (n > 0 && out == NULL) return REF_EINVAL;
+  uint32_t D = ceil_log2_u64(K);
+  uint64_t *sums = (uint64_t *)calloc(2ULL << D, sizeof(uint64_t));
+  uint64_t *cnt = (uint64_t *)calloc(2ULL << D, sizeof(uint64_t));
+  int rc = (sums && cnt) ? REF_OK : REF_ENOMEM;
+  if (rc == REF_OK) {
+    segment_tree(n, lengths, K, seed, D, sums, cnt);
+    ctx_t c = {0, n0, dense_ratio};
+    uint64_t base = 0, off = 0;
+    for (uint64_t i = 0; rc == REF_OK && i < K; ++i) {
+      uint64_t ni = cnt[(1ULL << D) + i];
+      if (counts) counts[i] = ni;
+      if (ni > 0) {
+        stream_t st = make_stream(seed, (1ULL << D) + i, P_SEGSEED, 0);
+        c.seed = stream_draw64(&st, 0);
+        sink_t k = {out + off, 0, ni};
+        rc = sample_r(&c, 1, base, lengths[i], ni, 0, &k);
+      }
+      base += lengths[i];
+      off += ni;
+    }
+  }
+  free(sums);
+  free(cnt);
+  return rc;
 }
 
 /* --- primitives, exported so that the tests can pin each one ----------- */

@@ -58,6 +58,15 @@ MUTANTS = [
     ("bernoulli skip off by one", "        double np = (double)pos + (double)g + 1.0;",
      "        double np = (double)pos + (double)g + 2.0;"),
     ("geometric uniform scale", "  return x * 0x1p-32f;", "  return x * 0x1p-31f;"),
+    ("segment split sizes swapped", "hyp_stream(cnt[id], Ll, Ll + Lr, seed, id, P_SEGSPLIT)",
+     "hyp_stream(cnt[id], Lr, Ll + Lr, seed, id, P_SEGSPLIT)"),
+    ("segment upward sum drops right subtree",
+     "sums[first + a] = sums[2 * (first + a)] + sums[2 * (first + a) + 1];",
+     "sums[first + a] = sums[2 * (first + a)];"),
+    ("segment values not shifted", "rc = sample_r(&c, 1, base, lengths[i], ni, 0, &k);",
+     "rc = sample_r(&c, 1, 0, lengths[i], ni, 0, &k);"),
+    ("segments share one seed", "        c.seed = stream_draw64(&st, 0);", "        c.seed = seed;"),
+    ("segment tree one level short", "  for (uint32_t j = D; j >= 1; --j) {", "  for (uint32_t j = D; j >= 2; --j) {"),
 ]
 
 
@@ -224,6 +233,39 @@ def pin_failures(L) -> list:
                 obs[idx[t]] += 1
             return _chisq_pvalue(obs, probs) > 1e-4
         check("with replacement", replacement)
+
+        def segments():
+            # per-segment counts: multivariate hypergeometric
+            L, n = [2, 0, 3, 1, 2], 3
+            N = sum(L)
+            vecs = [v for v in itertools.product(*[range(x + 1) for x in L]) if sum(v) == n]
+            probs = [math.prod(math.comb(x, k) for x, k in zip(L, v)) / math.comb(N, n)
+                     for v in vecs]
+            idx = {v: i for i, v in enumerate(vecs)}
+            obs = np.zeros(len(vecs))
+            for seed in range(8000):
+                _, c = oracle.sample_segments(n, L, seed, n0=2)
+                obs[idx[tuple(int(x) for x in c)]] += 1
+            if _chisq_pvalue(obs, probs) < 1e-4:
+                return False
+            # all subsets of two equal segments
+            cells = list(itertools.combinations(range(1, 7), 2))
+            ci = {c: i for i, c in enumerate(cells)}
+            obs = np.zeros(len(cells))
+            for seed in range(6000):
+                v, _ = oracle.sample_segments(2, [3, 3], seed, n0=2)
+                t = tuple(int(x) for x in v)
+                if t not in ci:
+                    return False
+                obs[ci[t]] += 1
+            if _chisq_pvalue(obs, np.full(len(cells), 1 / len(cells))) < 1e-4:
+                return False
+            # counts add up on the paper's 13-PE example and land in their segments
+            L13 = [20, 15, 30, 5, 17, 25, 10, 22, 18, 12, 20, 15, 20]
+            v, c = oracle.sample_segments(50, L13, 3, n0=8)
+            per = np.histogram(v.astype(np.int64), bins=np.cumsum([0] + L13) + 0.5)[0]
+            return int(c.sum()) == 50 and per.tolist() == c.tolist()
+        check("uneven universe", segments)
     finally:
         oracle._lib = saved
     return bad
