@@ -298,6 +298,48 @@ def bench_parts(dcs, depths=(4, 8), reps: int = 3):
     return res
 
 
+def bench_segments(dcs, reps: int = 5):
+    """Uneven universe (Sec. 4.3): n = 2^28 of the concatenation of 4096
+    segments with sizes log-uniform in [2^16, 2^40] (about 2^48 elements),
+    against the plain sample of n of the same N; the segment-split kernel,
+    tree and leaf stage timed with HIP events."""
+    import torch
+    from paper_1610_05141_amd import workloads
+    stream = torch.cuda.current_stream()
+    L = workloads.segment_lengths(4096, 16, 40)
+    n, N, seed = 1 << 28, sum(L), SEED
+    res = {"workload": f"n=2^28 of {len(L)} segments, sizes log-uniform in [2^16, 2^40], "
+                       f"N={N}, seed={seed}"}
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(len(L), dtype=torch.int64, device="cuda")
+    cases = {
+        "segments": (lambda: dcs.sample_segments(n, L, seed, out=out, counts=cnt, stream=stream),
+                     {"split_ms": 8, "tree_ms": 1, "leaf_stage_ms": 2}),
+        "plain_same_n_N": (lambda: dcs.sample(n, N, seed, out=out, stream=stream),
+                           {"tree_ms": 1, "leaf_stage_ms": 2}),
+    }
+    for name, (run, kinds) in cases.items():
+        run()
+        dcs.synchronize(stream)
+        dcs.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / reps
+        r = {"ms_per_call": dt * 1e3, "samples_per_s": n / dt}
+        for key, kind in kinds.items():
+            k_ms, k_n = dcs.profile_read(kind)
+            r[key] = k_ms / max(k_n, 1)
+        dcs.profile_enable(False)
+        res[name] = r
+    d = out[1:] - out[:-1]
+    res["invariants_ok"] = bool((d > 0).all()) and int(out[0]) >= 1 and int(out[-1]) <= N
+    del out, cnt, d
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_graph(dcs, reps: int = 5):
     """Random graphs (Sec. 7): G(n, m) with m = 2^28 edges on n = 2^26
     vertices, and G(n, p) on the same vertices with p = 2^-23 (2^28 edges
@@ -392,9 +434,11 @@ def main() -> int:
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-parts", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-segments", action="store_true")
     ap.add_argument("--only", default=None,
                     help="comma list of other configurations (c1, c2b, c3a, c3b, batched, "
-                         "parts, graph, serving) to run alone, e.g. under a profiler; prints their lines only")
+                         "parts, graph, segments, serving) to run alone, e.g. under a profiler; "
+                         "prints their lines only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -408,7 +452,7 @@ def main() -> int:
     if args.only:
         names = args.only.split(",")
         res = {}
-        other = [x for x in names if x not in ("batched", "serving", "parts", "graph")]
+        other = [x for x in names if x not in ("batched", "serving", "parts", "graph", "segments")]
         if other:
             res.update(bench_other_configs(dcs, reps=args.steps, only=other))
         if "batched" in names:
@@ -417,6 +461,8 @@ def main() -> int:
             res["parts"] = bench_parts(dcs)
         if "graph" in names:
             res["graph"] = bench_graph(dcs)
+        if "segments" in names:
+            res["segments"] = bench_segments(dcs)
         if "serving" in names:
             res["serving"] = bench_serving(dcs)
         print(json.dumps(res), flush=True)
@@ -522,6 +568,9 @@ def main() -> int:
     if not args.no_graph:
         print("[bench] random graphs", file=sys.stderr, flush=True)
         rec["graph"] = bench_graph(dcs)
+    if not args.no_segments:
+        print("[bench] uneven universe", file=sys.stderr, flush=True)
+        rec["segments"] = bench_segments(dcs)
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         rec["serving"] = bench_serving(dcs)

@@ -195,6 +195,32 @@ int32_t dcs_sample_edges_gnp(uint64_t n_vertices, double p, uint64_t seed,
                              const dcs_params* params, uint32_t* uv_dev, uint64_t capacity,
                              uint64_t* count_dev, void* stream);
 
+/*
+ * dcs_sample_segments -- sampling over an uneven universe (Sec. 4.3, owner
+ * computes; Fig. 3): n distinct elements of the concatenation of K segments
+ * of lengths[0..K-1] elements (N = their sum), ascending as elements of
+ * 1..N.  The segments are the leaves of the paper's binomial tree: element
+ * counts are summed bottom-up and each inner node splits its sample count
+ * between its two subtrees by a hypergeometric deviate (keyed by the node);
+ * segment i then samples its count of its own elements as dcs_sample_ex
+ * does (Fig. 1), keyed by a seed hashed from the segment's identity.
+ *   lengths:    host array of K segment sizes, read during the call only.
+ *   out_dev:    n uint64 device slots: segment i's values (elements
+ *               lengths[0] + ... + lengths[i-1] + 1 .. that + lengths[i])
+ *               follow those of segments 0..i-1.
+ *   counts_dev: NULL, or K uint64 device slots receiving each segment's
+ *               number of values.
+ * The sample is a pure function of (n, lengths, seed, n0, dense_ratio).
+ * Errors: DCS_EINVAL if K == 0, K > DCS_MAX_SEGMENTS, lengths NULL, N >
+ * DCS_MAX_UNIVERSE, n > N, out_dev NULL with n > 0, or bad params.  Uses the
+ * library's workspace and a pinned host staging buffer (both grown on
+ * demand; may synchronize).
+ */
+#define DCS_MAX_SEGMENTS (1ull << 24)
+int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uint64_t seed,
+                            const dcs_params* params, uint64_t* out_dev, uint64_t* counts_dev,
+                            void* stream);
+
 /* A capacity that the Bernoulli count exceeds with negligible probability:
  * Np + 10 sqrt(Np(1-p)) + 64. */
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N);
@@ -344,7 +370,8 @@ const char* dcs_status_string(int32_t status);
  * jobs over power-of-two ranges,
  * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
  * kernel of the dense jobs with ranges up to 2^16, 7 = edge-index
- * decoding of the graph entry points); DCS_EINVAL for another kind. */
+ * decoding of the graph entry points, 8 = the segment splits of
+ * dcs_sample_segments); DCS_EINVAL for another kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 /* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "DcsError", "lib", "sample", "sample_noalloc", "sample_replacement", "sample_bernoulli", "sample_part",
-    "sample_edges_gnm", "sample_edges_gnp",
+    "sample_segments", "sample_edges_gnm", "sample_edges_gnp",
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
@@ -32,7 +32,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 EXPORTED_SYMBOLS = (
     "dcs_sample", "dcs_sample_ex", "dcs_sample_noalloc", "dcs_sample_replacement", "dcs_sample_replacement_ex",
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
-    "dcs_sample_part", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
+    "dcs_sample_part", "dcs_sample_segments", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
     "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
                                               ctypes.c_size_t, vp]),
             "dcs_bernoulli_capacity_hint": (u64, [dbl, u64]),
             "dcs_sample_part": (i32, [i32, u64, u64, u64, pp, u32, u64, vp, u64, vp, vp]),
+            "dcs_sample_segments": (i32, [u64, vp, u64, u64, pp, vp, vp, vp]),
             "dcs_sample_edges_gnm": (i32, [u64, u64, u64, pp, vp, vp]),
             "dcs_sample_edges_gnp": (i32, [u64, dbl, u64, pp, vp, u64, vp, vp]),
             "dcs_workspace_size": (i32, [i32, u64, u64, dbl, pp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -223,6 +224,25 @@ def sample_part(n: int, N: int, seed: int, depth: int, index: int, out=None, cap
                                _ptr(out), capacity, _ptr(count_rank), _stream_handle(stream))
     _check(rc, "dcs_sample_part")
     return out, count_rank
+
+
+def sample_segments(n: int, lengths, seed: int, out=None, counts=None, stream=None, n0=None,
+                    dense_ratio=None):
+    """n distinct elements of the concatenation of segments of the given
+    lengths (a host sequence), ascending as elements of 1..sum(lengths)
+    (Sec. 4.3).  Returns (out, counts): counts is a K-element int64 CUDA
+    tensor with each segment's number of values."""
+    import numpy as np
+    import torch
+    L = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint64))
+    out = _out_tensor(out, n)
+    if counts is None:
+        counts = torch.empty(max(L.size, 1), dtype=torch.int64, device="cuda")
+    rc = lib().dcs_sample_segments(n, ctypes.c_void_p(L.ctypes.data), L.size, seed,
+                                   _params(n0, dense_ratio), _ptr(out), _ptr(counts),
+                                   _stream_handle(stream))
+    _check(rc, "dcs_sample_segments")
+    return out, counts
 
 
 def _edge_tensor(out, m: int):
@@ -370,8 +390,8 @@ def profile_read(kind: int):
     """(total milliseconds, launches) of kernel kind 0 reset, 1 tree, 2 leaf
     stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse and
     with-replacement jobs over power-of-two ranges, 5 work-group leaf kernel
-    of the other jobs, 6
-    one-wave dense leaf kernel, accumulated since profile_enable (read after
+    of the other jobs, 6 one-wave dense leaf kernel, 7 edge decoding, 8
+    segment splits, accumulated since profile_enable (read after
     synchronize)."""
     ms = ctypes.c_double(0)
     n = ctypes.c_uint64(0)

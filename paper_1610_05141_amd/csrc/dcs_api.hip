@@ -216,8 +216,9 @@ void release_timings() {
 }
 // kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
 // 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
-// the rest, 6 one-wave dense leaf kernel, 7 edge-index decoding
-constexpr int kProfKinds = 8;
+// the rest, 6 one-wave dense leaf kernel, 7 edge-index decoding, 8 splits
+// of the segments of an uneven universe
+constexpr int kProfKinds = 9;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 
@@ -292,6 +293,29 @@ int32_t own_workspace(DeviceCtx* c, size_t bytes, void** ws) {
     c->ws_bytes = grow;
   }
   *ws = c->ws;
+  return DCS_OK;
+}
+
+// Copies `bytes` from host memory to `dst` on stream `s` through the
+// device's pinned staging buffer (grown on demand), so that the caller's
+// memory is free again when this returns and the copy stays asynchronous.
+int32_t stage_upload(DeviceCtx* c, const void* src, size_t bytes, void* dst, hipStream_t s) {
+  if (c->stage_done != nullptr && hipEventSynchronize(c->stage_done) != hipSuccess) return DCS_EHIP;
+  if (c->stage_bytes < bytes) {
+    if (c->stage != nullptr && hipHostFree(c->stage) != hipSuccess) return DCS_EHIP;
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    const size_t grow = std::max(bytes, static_cast<size_t>(1) << 20);
+    if (hipHostMalloc(&c->stage, grow, hipHostMallocDefault) != hipSuccess) return DCS_ENOMEM;
+    c->stage_bytes = grow;
+  }
+  if (c->stage_done == nullptr &&
+      hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess)
+    return DCS_EHIP;
+  memcpy(c->stage, src, bytes);
+  if (hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(c->stage_done, s) != hipSuccess)
+    return DCS_EHIP;
   return DCS_OK;
 }
 
@@ -515,6 +539,81 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
                            pl.stack_depth, out_dev, static_cast<hipStream_t>(stream),
                            error_word(c, stream),
                            leaf_wgs_for(c, static_cast<uint32_t>(variant), np), count_rank_dev);
+}
+
+int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uint64_t seed,
+                            const dcs_params* params, uint64_t* out_dev, uint64_t* counts_dev,
+                            void* stream) {
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (K == 0 || K > DCS_MAX_SEGMENTS || lengths == nullptr) return DCS_EINVAL;
+  uint64_t N = 0;
+  for (uint64_t i = 0; i < K; ++i) {
+    if (lengths[i] > DCS_MAX_UNIVERSE - N) return DCS_EINVAL;
+    N += lengths[i];
+  }
+  if (n > N || (n > 0 && out_dev == nullptr)) return DCS_EINVAL;
+  if (n == 0 && counts_dev == nullptr) return DCS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  uint32_t D = 0;
+  while ((1ull << D) < K) ++D;
+  // Plan every segment for its expected count (at least one tree thread for
+  // any segment that may hold samples).  The plan only spreads the work: the
+  // DFS below each segment's cut follows the actual count, its stack bound
+  // depends on the segment's range alone, and the leaf capacity bounds the
+  // leaves of all segments together (at most 4 n/n0 + 5 per non-empty
+  // segment, plus the leaves of levels forced by ranges above 2^32).
+  std::vector<Instance> tab(K);
+  uint64_t tb = 0, tt = 0, forced_leaves = 0, nonempty = 0;
+  uint32_t stack_depth = 1;
+  uint64_t base = 0;
+  for (uint64_t i = 0; i < K; ++i) {
+    Instance& I = tab[i];
+    I = Instance{};
+    I.N = lengths[i];
+    I.base = base;
+    I.n0 = P.n0;
+    I.dense_ratio = P.dense_ratio;
+    I.thread_base = tb;
+    I.top_base = tt;
+    base += lengths[i];
+    if (n == 0 || lengths[i] == 0) continue;
+    const double m = static_cast<double>(n) *
+                     (static_cast<double>(lengths[i]) / static_cast<double>(N));
+    const uint64_t est = std::max<uint64_t>(1, std::min<uint64_t>(lengths[i], static_cast<uint64_t>(m)));
+    const Plan pl = make_plan(est, lengths[i], P.n0, 0, cut_bias_for(0, est));
+    I.cut = pl.cut;
+    I.top_cut = pl.top_cut;
+    tb += pl.threads;
+    tt += pl.top_threads;
+    stack_depth = std::max(stack_depth, pl.stack_depth);
+    uint32_t forced = 0;
+    while (ceil_div_pow2(lengths[i], forced) > kLeafRange) ++forced;
+    if (forced > 0) forced_leaves += std::min<uint64_t>(n, 2ull << forced);
+    ++nonempty;
+  }
+  const uint64_t leaf_cap =
+      4 * ((n + P.n0 - 1) / P.n0) + 64 + 5 * nonempty + std::min<uint64_t>(n, forced_leaves);
+  const TreeLayout L = tree_layout(static_cast<uint32_t>(K), leaf_cap, tb, stack_depth, tt);
+  void* ws = nullptr;
+  rc = own_workspace(c, L.total, &ws);
+  if (rc) return rc;
+  Instance* inst = reinterpret_cast<Instance*>(static_cast<char*>(ws) + L.inst);
+  rc = stage_upload(c, tab.data(), sizeof(Instance) * K, inst, s);
+  if (rc) return rc;
+  Timing t8{};
+  timing_begin(8, s, &t8);
+  hipError_t e = dcs::launch_segments(inst, K, D, n, N, seed, counts_dev, s);
+  timing_end(s, &t8);
+  if (e != hipSuccess) return DCS_EHIP;
+  if (n == 0) return DCS_OK;
+  return run_tree_pipeline(c, ws, L, nullptr, static_cast<uint32_t>(K), tb, tt, leaf_cap,
+                           stack_depth, out_dev, s, error_word(c, stream),
+                           leaf_wgs_for(c, 0, n));
 }
 
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N) {

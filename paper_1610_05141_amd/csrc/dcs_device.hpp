@@ -33,6 +33,8 @@ enum Purpose : uint32_t {
   kBChunk = 5,   // Bernoulli sampling: geometric skips of one chunk
   kWrSplit = 6,  // binomial split of a with-replacement node
   kWrLeaf = 7,   // with-replacement leaf: uniform offsets
+  kSegSplit = 8, // uneven universe: split of a subtree of segments
+  kSegSeed = 9,  // uneven universe: seed of one segment's own tree
 };
 
 constexpr uint64_t kMaxUniverse = 1ull << 52;
@@ -382,15 +384,16 @@ __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N,
 }
 
 // Hyp(n, M, N): successes among n draws without replacement from N items, M
-// of them successes; stream (seed, node, SPLIT, 0).  kWave: called by all 64
-// lanes of a wave with the same arguments.
+// of them successes; stream (seed, node, purpose, 0), purpose SPLIT for the
+// recursion tree.  kWave: called by all 64 lanes of a wave with the same
+// arguments.
 template <bool kWave = false>
 __device__ __forceinline__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t seed,
-                                   uint64_t node) {
+                                   uint64_t node, uint32_t purpose = kSplit) {
   if (n == 0 || M == 0) return 0;
   if (M == N) return n;
   if (n == N) return M;
-  Draws64 d{make_stream(seed, node, kSplit, 0), 0};
+  Draws64 d{make_stream(seed, node, purpose, 0), 0};
   const bool flip_n = n > N - n;
   const uint64_t n1 = flip_n ? N - n : n;
   const bool flip_m = M > N - M;

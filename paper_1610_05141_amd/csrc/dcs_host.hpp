@@ -56,6 +56,11 @@ struct DeviceCtx {
   // device address of this device's copy of the allocation-free entry
   // point's static scratch array (hipGetSymbolAddress at set-up)
   void* noalloc_scratch = nullptr;
+  // pinned host buffer for instance tables uploaded by single calls, and the
+  // event after its last copy (waited for before it is written again)
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
   // the library's error words on this device (kErrSlots of them) and the
   // stream each one serves; slot 0 is the null stream's, the last one is
   // shared by streams beyond the others

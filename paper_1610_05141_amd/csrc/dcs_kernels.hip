@@ -1366,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ i
   const Instance I = inst[find_instance(inst, n_inst, t, true)];
   const uint64_t g = t - I.top_base;
   const bool lane0 = (threadIdx.x & 63u) == 0;
-  Node v{1, 0, I.N, I.n, 0};
+  Node v{1, I.base, I.N, I.n, 0};
   uint32_t d0 = 0;
   if (part_out != nullptr) {
     const bool inner = part_root(v, I.part_depth, I.part, I);
@@ -1426,6 +1426,47 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     if (sp == 0) break;
     v = stk[--sp];
   }
+}
+
+// Uneven universe (Sec. 4.3): thread i follows the binomial tree of the K
+// segments from the root (level D) down to segment i.  At level j the
+// subtree holding segment i is a = i >> j (segments a 2^j .. min(a 2^j + 2^j,
+// K) - 1, heap id 2^(D-j) + a); its left subtree takes Hyp(n', L_l, L_l + L_r)
+// of its n' samples, keyed by that id with the SEGSPLIT purpose.  Every path
+// recomputes the splits above it, which are the same on every path (Sec. 3.2:
+// decisions keyed by the node's identity), and sums the left counts it
+// passes: the segment's output offset.  Element counts of subtrees come from
+// the segments' bases (prefix sums the host stored).  The segment's own tree
+// is keyed by 64-bit draw 0 of (seed, 2^D + i, SEGSEED).
+__global__ __launch_bounds__(256) void k_segments(Instance* inst, uint64_t K, uint32_t D,
+                                                  uint64_t n, uint64_t N, uint64_t seed,
+                                                  uint64_t* counts) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  uint64_t nv = n, off = 0;
+  for (uint32_t j = D; j >= 1; --j) {
+    const uint64_t a = i >> j;
+    const uint64_t first = a << j;
+    const uint64_t mid = first + (1ull << (j - 1));
+    const uint64_t end = first + (1ull << j);
+    const uint64_t p_first = inst[first].base;
+    const uint64_t p_mid = mid < K ? inst[mid].base : N;
+    const uint64_t p_end = end < K ? inst[end].base : N;
+    const uint64_t Ll = p_mid - p_first;
+    const uint64_t all = p_end - p_first;
+    const uint64_t nl = hypergeometric(nv, Ll, all, seed, (1ull << (D - j)) + a, kSegSplit);
+    if ((i >> (j - 1)) & 1) {
+      nv -= nl;
+      off += nl;
+    } else {
+      nv = nl;
+    }
+  }
+  const uint4 b = philox_block(make_stream(seed, (1ull << D) + i, kSegSeed, 0), 0);
+  inst[i].n = nv;
+  inst[i].seed = static_cast<uint64_t>(b.x) | (static_cast<uint64_t>(b.y) << 32);
+  inst[i].out_offset = off;
+  if (counts != nullptr) counts[i] = nv;
 }
 
 __device__ inline void start_control(Control* ctl, unsigned int* err) {
@@ -1943,6 +1984,14 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                        static_cast<size_t>(lds_cap) * sizeof(uint32_t), stream, N, seed, chunk,
                        n_chunks, c64, status, out, capacity, count_dev, ctl, lds_cap, tickets,
                        n_cls);
+  return hipGetLastError();
+}
+
+hipError_t launch_segments(Instance* inst, uint64_t K, uint32_t D, uint64_t n, uint64_t N,
+                           uint64_t seed, uint64_t* counts, hipStream_t stream) {
+  const uint64_t blocks = (K + 255) / 256;
+  hipLaunchKernelGGL(k_segments, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
+                     K, D, n, N, seed, counts);
   return hipGetLastError();
 }
 

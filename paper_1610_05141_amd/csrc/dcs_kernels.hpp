@@ -26,6 +26,9 @@ struct Instance {
   uint32_t part_depth;
   uint64_t part;
   uint64_t part_cap;    // nothing is sampled if the part holds more values
+  // Elements before this instance's range: its root covers base+1 .. base+N
+  // (0 except for the segments of an uneven universe).
+  uint64_t base;
 };
 
 // A recursion-tree node (Fig. 1): node id (root 1, children 2i, 2i+1), the
@@ -139,6 +142,11 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,
                             uint64_t* count_dev, Control* ctl, unsigned long long* tickets,
                             uint32_t grid, uint32_t lds_cap, hipStream_t stream);
+// Uneven universe: fills count, seed and output offset of the K segment
+// instances (their base and N set) from the splits of the binomial tree of
+// depth D over them; counts (may be null) receives the K counts.
+hipError_t launch_segments(Instance* inst, uint64_t K, uint32_t D, uint64_t n, uint64_t N,
+                           uint64_t seed, uint64_t* counts, hipStream_t stream);
 hipError_t launch_bernoulli_fill(uint64_t N, uint64_t* out, uint64_t capacity,
                                  uint64_t* count_dev, hipStream_t stream);
 hipError_t launch_debug(int op, const void* x, const void* x2, void* y, uint64_t count,

@@ -65,3 +65,11 @@ def poisson_arrivals(count: int, rate_per_s: float, key: int = WORKLOAD_KEY) -> 
         t += -math.log1p(-u) / rate_per_s
         times.append(t)
     return times
+
+
+def segment_lengths(count: int = 4096, lo_log2: float = 16, hi_log2: float = 40,
+                    key: int = WORKLOAD_KEY) -> list:
+    """Sizes of the segments of an uneven universe (sharded data of uneven
+    shard sizes): segment i holds floor(2^(lo + (hi-lo) u)) elements."""
+    return [int(math.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * uniform(key ^ 0x5E6, i, 4))))
+            for i in range(count)]
