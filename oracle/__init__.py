@@ -23,6 +23,7 @@ CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 # Stream purposes (same meaning as the library's; restated here on purpose).
 P_SPLIT, P_LEAF, P_BERN, P_REPAIR, P_BCHUNK, P_WRSPLIT, P_WRLEAF = 1, 2, 3, 4, 5, 6, 7
 P_SEGSPLIT, P_SEGSEED = 8, 9
+P_WCHUNK, P_WREPAIR = 10, 11
 
 DEFAULT_N0 = 4096
 DEFAULT_DENSE_RATIO = 16
@@ -93,6 +94,8 @@ def configure(L: ctypes.CDLL) -> ctypes.CDLL:
             "dcs_ref_bin_batch": (None, [u64, u64, u64, u64, u64, u64, p64]),
             "dcs_ref_range_map_counts": (None, [u64, p64, p64]),
             "dcs_ref_segment_tree": (i32, [u64, p64, u64, u64, p64, p64]),
+            "dcs_ref_sample_wholerange": (i32, [u64, u64, u64, u32, p64, p32]),
+            "dcs_ref_wholerange_hits": (i32, [u64, u64, u64, u32, u32, p64, u64, p64]),
             "dcs_ref_sample_segments": (i32, [u64, p64, u64, u64, u32, u32, p64, p64]),
         }
         for name, (res, args) in sig.items():
@@ -190,6 +193,27 @@ def sample_segments(n: int, lengths, seed: int, n0: int = DEFAULT_N0,
     _check(lib().dcs_ref_sample_segments(n, _p64(L), len(L), seed, n0, dense_ratio, _p64(out),
                                          _p64(counts)), "sample_segments")
     return out[:n].copy(), counts[:len(L)].copy()
+
+
+def sample_wholerange(n: int, N: int, seed: int, n0: int = DEFAULT_N0) -> tuple:
+    """n of 1..N by Algorithm B over the whole range with the repair (Sec. 2,
+    Sec. 4.7, Sec. 5's GPU variant): (values, accepted attempt)."""
+    out = np.empty(max(n, 1), dtype=np.uint64)
+    att = (ctypes.c_uint32 * 1)()
+    _check(lib().dcs_ref_sample_wholerange(n, N, seed, n0, _p64(out), att),
+           "sample_wholerange")
+    return out[:n].copy(), int(att[0])
+
+
+def wholerange_hits(n: int, N: int, seed: int, attempt: int = 0, n0: int = DEFAULT_N0,
+                    cap: int = 0) -> tuple:
+    """(n', first min(n', cap) hit positions + 1) of one attempt."""
+    out = np.empty(max(cap, 1), dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    _check(lib().dcs_ref_wholerange_hits(n, N, seed, n0, attempt, _p64(out), cap, _p64(cnt)),
+           "wholerange_hits")
+    c = int(cnt[0])
+    return c, out[:min(c, cap)].copy()
 
 
 def edge_pair(k: int) -> tuple:

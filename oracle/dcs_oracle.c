@@ -68,7 +68,9 @@ enum {
   P_WRSPLIT = 6, /* binomial split of a with-replacement node */
   P_WRLEAF = 7,  /* with-replacement leaf: uniform offsets */
   P_SEGSPLIT = 8, /* uneven universe: split of a subtree of segments */
-  P_SEGSEED = 9   /* uneven universe: the seed of one segment's own tree */
+  P_SEGSEED = 9,  /* uneven universe: the seed of one segment's own tree */
+  P_WCHUNK = 10,  /* whole-range Algorithm B: skips of one chunk */
+  P_WREPAIR = 11  /* whole-range Algorithm B: which hits to remove */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -1029,6 +1031,111 @@ EXPORT int dcs_ref_sample_segments(uint64_t n, const uint64_t *lengths, uint64_t
   free(sums);
   free(cnt);
   return rc;
+}
+
+/* Algorithm B over the whole range (Sec. 2, with the skips and prefix sums of
+ * Sec. 4.7, as the paper's GPU variant of Sec. 5 runs it, minus its host
+ * round trip): n of 1..N without replacement, for 1 <= N <= 2^32 and
+ * rho >= 2^-10.
+ *   rho = min(1, (n + 8 isqrt(n) + 16) / N) in double;
+ *   attempt a = 0, 1, ...: the Bernoulli(rho) hits of 0..N-1 by the chunks
+ *     and single-precision skips of Sec. 4.7's variant (chunk j keyed by
+ *     (j, WCHUNK, a)); rho = 1 makes every element a hit;
+ *   accept iff n <= n' <= n + 16 isqrt(n) + 64 for the hit count n' (any
+ *   rule on n' alone keeps the sample uniform), else the next attempt;
+ *   remove the hits whose index (0-based, in position order) is one of the
+ *   first n' - n distinct non-void values of (0, WREPAIR, a) mapped into
+ *   [0, n') -- Algorithm H's rule;
+ *   output the remaining positions + 1, ascending.
+ * *attempt_out receives the accepted attempt. */
+#define REF_WB_MIN_RHO 0x1p-10
+
+static uint64_t wb_rho_num(uint64_t n) { return n + 8 * isqrt_u64(n) + 16; }
+
+static int wb_check(uint64_t n, uint64_t N, double *rho) {
+  if (N == 0 || N > (1ULL << 32) || n > N) return REF_EINVAL;
+  uint64_t num = wb_rho_num(n);
+  *rho = num >= N ? 1.0 : (double)num / (double)N;
+  if (n > 0 && *rho < REF_WB_MIN_RHO) return REF_EINVAL;
+  return REF_OK;
+}
+
+/* Hits of attempt a: positions into pos[0..cap) while they fit; returns n'. */
+static uint64_t wb_hits(double rho, uint64_t N, uint64_t seed, uint32_t n0, uint32_t attempt,
+                        uint64_t *pos, uint64_t cap) {
+  uint64_t got = 0;
+  if (rho >= 1.0) {
+    for (uint64_t i = 0; i < N; ++i) {
+      if (got < cap) pos[got] = i;
+      ++got;
+    }
+    return got;
+  }
+  uint64_t C = bern_chunk(rho, n0);
+  float c32 = (float)(1.0 / log1p64(-rho));
+  for (uint64_t base = 0, j = 0; base < N; base += C, ++j) {
+    uint64_t len = (N - base) < C ? (N - base) : C;
+    stream_t s = make_stream(seed, j, P_WCHUNK, attempt);
+    int64_t q = -1;
+    for (uint64_t t = 0;; ++t) {
+      float g = floorf(log32(u32_geom(stream_word(&s, t))) * c32);
+      double nq = (double)q + (double)g + 1.0;
+      if (nq >= (double)len) break;
+      q = (int64_t)nq;
+      if (got < cap) pos[got] = base + (uint64_t)q;
+      ++got;
+    }
+  }
+  return got;
+}
+
+EXPORT int dcs_ref_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
+                                     uint64_t *out, uint32_t *attempt_out) {
+  double rho;
+  if (n0 < 2 || n0 > 4096 || wb_check(n, N, &rho) != REF_OK) return REF_EINVAL;
+  if (attempt_out) *attempt_out = 0;
+  if (n == 0) return REF_OK;
+  if (out == NULL) return REF_EINVAL;
+  uint64_t hi = n + 16 * isqrt_u64(n) + 64;
+  uint64_t *pos = (uint64_t *)malloc((hi + 1) * sizeof(uint64_t));
+  uint64_t *rem = (uint64_t *)malloc((hi - n + 1) * sizeof(uint64_t));
+  int rc = (pos && rem) ? REF_OK : REF_ENOMEM;
+  for (uint32_t a = 0; rc == REF_OK; ++a) {
+    uint64_t nh = wb_hits(rho, N, seed, n0, a, pos, hi + 1);
+    if (nh < n || nh > hi) continue;
+    uint64_t r = nh - n;
+    if (r > 0) {
+      stream_t sr = make_stream(seed, 0, P_WREPAIR, a);
+      rc = first_distinct_sorted(&sr, r, nh, rem);
+      if (rc != REF_OK) break;
+    }
+    uint64_t j = 0, o = 0;
+    for (uint64_t h = 0; h < nh; ++h) {
+      if (j < r && rem[j] == h) { ++j; continue; }
+      out[o++] = pos[h] + 1;
+    }
+    if (attempt_out) *attempt_out = a;
+    break;
+  }
+  free(pos);
+  free(rem);
+  return rc;
+}
+
+/* The hit count n' of one attempt (for the law of n'), and its first
+ * min(n', cap) positions + 1. */
+EXPORT int dcs_ref_wholerange_hits(uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
+                                   uint32_t attempt, uint64_t *out, uint64_t cap,
+                                   uint64_t *count) {
+  double rho;
+  if (n0 < 2 || n0 > 4096 || wb_check(n, N, &rho) != REF_OK || count == NULL) return REF_EINVAL;
+  if (cap > 0 && out == NULL) return REF_EINVAL;
+  uint64_t *pos = (uint64_t *)malloc((cap + 1) * sizeof(uint64_t));
+  if (!pos) return REF_ENOMEM;
+  *count = wb_hits(rho, N, seed, n0, attempt, pos, cap);
+  for (uint64_t i = 0; i < cap && i < *count; ++i) out[i] = pos[i] + 1;
+  free(pos);
+  return REF_OK;
 }
 
 /* --- primitives, exported so that the tests can pin each one ----------- */

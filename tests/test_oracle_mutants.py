@@ -66,6 +66,13 @@ MUTANTS = [
     ("segment values not shifted", "rc = sample_r(&c, 1, base, lengths[i], ni, 0, &k);",
      "rc = sample_r(&c, 1, 0, lengths[i], ni, 0, &k);"),
     ("segments share one seed", "        c.seed = stream_draw64(&st, 0);", "        c.seed = seed;"),
+    ("wholerange output off by one", "      out[o++] = pos[h] + 1;", "      out[o++] = pos[h];"),
+    ("wholerange repair range short", "rc = first_distinct_sorted(&sr, r, nh, rem);",
+     "rc = first_distinct_sorted(&sr, r, nh - 1, rem);"),
+    ("wholerange skip gap", "      double nq = (double)q + (double)g + 1.0;",
+     "      double nq = (double)q + (double)g + 2.0;"),
+    ("wholerange removes neighbour", "      if (j < r && rem[j] == h) { ++j; continue; }",
+     "      if (j < r && rem[j] == h + 1) { ++j; continue; }"),
     ("segment tree one level short", "  for (uint32_t j = D; j >= 1; --j) {", "  for (uint32_t j = D; j >= 2; --j) {"),
 ]
 
@@ -266,6 +273,23 @@ def pin_failures(L) -> list:
             per = np.histogram(v.astype(np.int64), bins=np.cumsum([0] + L13) + 0.5)[0]
             return int(c.sum()) == 50 and per.tolist() == c.tolist()
         check("uneven universe", segments)
+
+        def wholerange():
+            n, N = 2, 40
+            cells = list(itertools.combinations(range(1, N + 1), n))
+            ci = {c: i for i, c in enumerate(cells)}
+            obs = np.zeros(len(cells))
+            for seed in range(12000):
+                v, _ = oracle.sample_wholerange(n, N, seed, n0=16)
+                t = tuple(int(x) for x in v)
+                if t not in ci:
+                    return False
+                obs[ci[t]] += 1
+            if _chisq_pvalue(obs, np.full(len(cells), 1 / len(cells))) < 1e-4:
+                return False
+            v, _ = oracle.sample_wholerange(30, 40, 3, n0=16)
+            return v.size == 30 and len(set(v.tolist())) == 30 and 1 <= v.min() and v.max() <= 40
+        check("whole-range B", wholerange)
     finally:
         oracle._lib = saved
     return bad
