@@ -221,6 +221,26 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
                             const dcs_params* params, uint64_t* out_dev, uint64_t* counts_dev,
                             void* stream);
 
+/*
+ * dcs_sample_wholerange -- n distinct integers of 1..N, ascending, by
+ * Algorithm B over the whole range (Sec. 2; Sec. 4.7's skips and prefix
+ * sums; the GPU variant of Sec. 5, with the removal of the excess hits done
+ * on the device instead of on the host): a Bernoulli sample with
+ * rho = min(1, (n + 8 isqrt(n) + 16)/N) by fixed chunks, repeated while it
+ * holds fewer than n hits (or more than n + 16 isqrt(n) + 64), then the
+ * hits whose indices are the first n' - n distinct values of a uniform
+ * stream over [0, n') are removed.  A second, independent path for dense
+ * samples beside dcs_sample's tree (a different sample for the same seed).
+ *   out_dev: n uint64 device slots, written in full.
+ * The device makes up to two attempts (both failing has probability below
+ * about 1e-20); if both are rejected, dcs_synchronize reports DCS_EDEVICE.
+ * Errors: DCS_EINVAL if N == 0, N > 2^32, n > N, out_dev NULL with n > 0
+ * or bad params; DCS_ENOTSUP if 0 < n and rho < 2^-10 (sparse samples:
+ * use dcs_sample).  Uses the library's workspace.
+ */
+int32_t dcs_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                              uint64_t* out_dev, void* stream);
+
 /* A capacity that the Bernoulli count exceeds with negligible probability:
  * Np + 10 sqrt(Np(1-p)) + 64. */
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N);
@@ -371,7 +391,9 @@ const char* dcs_status_string(int32_t status);
  * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
  * kernel of the dense jobs with ranges up to 2^16, 7 = edge-index
  * decoding of the graph entry points, 8 = the segment splits of
- * dcs_sample_segments); DCS_EINVAL for another kind. */
+ * dcs_sample_segments, 9 / 10 / 11 = the count passes / the scan and
+ * repair / the write passes of dcs_sample_wholerange); DCS_EINVAL for
+ * another kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 /* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "DcsError", "lib", "sample", "sample_noalloc", "sample_replacement", "sample_bernoulli", "sample_part",
-    "sample_segments", "sample_edges_gnm", "sample_edges_gnp",
+    "sample_segments", "sample_wholerange", "sample_edges_gnm", "sample_edges_gnp",
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
@@ -32,7 +32,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 EXPORTED_SYMBOLS = (
     "dcs_sample", "dcs_sample_ex", "dcs_sample_noalloc", "dcs_sample_replacement", "dcs_sample_replacement_ex",
     "dcs_sample_bernoulli", "dcs_sample_bernoulli_ex", "dcs_bernoulli_capacity_hint",
-    "dcs_sample_part", "dcs_sample_segments", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
+    "dcs_sample_part", "dcs_sample_segments", "dcs_sample_wholerange", "dcs_sample_edges_gnm", "dcs_sample_edges_gnp",
     "dcs_workspace_size", "dcs_batch_create", "dcs_batch_run", "dcs_batch_destroy",
     "dcs_batch_total", "dcs_synchronize", "dcs_status_string", "dcs_profile_enable",
     "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "dcs_bernoulli_capacity_hint": (u64, [dbl, u64]),
             "dcs_sample_part": (i32, [i32, u64, u64, u64, pp, u32, u64, vp, u64, vp, vp]),
             "dcs_sample_segments": (i32, [u64, vp, u64, u64, pp, vp, vp, vp]),
+            "dcs_sample_wholerange": (i32, [u64, u64, u64, pp, vp, vp]),
             "dcs_sample_edges_gnm": (i32, [u64, u64, u64, pp, vp, vp]),
             "dcs_sample_edges_gnp": (i32, [u64, dbl, u64, pp, vp, u64, vp, vp]),
             "dcs_workspace_size": (i32, [i32, u64, u64, dbl, pp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -243,6 +244,17 @@ def sample_segments(n: int, lengths, seed: int, out=None, counts=None, stream=No
                                    _stream_handle(stream))
     _check(rc, "dcs_sample_segments")
     return out, counts
+
+
+def sample_wholerange(n: int, N: int, seed: int, out=None, stream=None, n0=None):
+    """n distinct values of 1..N (N <= 2^32, n/N not below about 2^-10),
+    ascending, by Algorithm B over the whole range with the repair on the
+    device (Sec. 2, 4.7, 5)."""
+    out = _out_tensor(out, n)
+    rc = lib().dcs_sample_wholerange(n, N, seed, _params(n0, None), _ptr(out),
+                                     _stream_handle(stream))
+    _check(rc, "dcs_sample_wholerange")
+    return out
 
 
 def _edge_tensor(out, m: int):
@@ -391,8 +403,8 @@ def profile_read(kind: int):
     stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse and
     with-replacement jobs over power-of-two ranges, 5 work-group leaf kernel
     of the other jobs, 6 one-wave dense leaf kernel, 7 edge decoding, 8
-    segment splits, accumulated since profile_enable (read after
-    synchronize)."""
+    segment splits, 9 / 10 / 11 whole-range B count / repair / write,
+    accumulated since profile_enable (read after synchronize)."""
     ms = ctypes.c_double(0)
     n = ctypes.c_uint64(0)
     _check(lib().dcs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dcs_profile_read")

@@ -217,8 +217,9 @@ void release_timings() {
 // kinds: 0 reset, 1 tree, 2 leaf stage (all leaf kernels), 3 Bernoulli,
 // 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
 // the rest, 6 one-wave dense leaf kernel, 7 edge-index decoding, 8 splits
-// of the segments of an uneven universe
-constexpr int kProfKinds = 9;
+// of the segments of an uneven universe, 9 / 10 / 11 whole-range
+// Algorithm B: count passes / scan and repair / write passes
+constexpr int kProfKinds = 12;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 
@@ -235,6 +236,7 @@ int32_t device_ctx(DeviceCtx** out) {
     c.cus = prop.multiProcessorCount;
     c.leaf_occupancy = dcs::leaf_occupancy();
     c.bern_wave_occupancy = dcs::bern_wave_occupancy();
+    c.wb_occupancy = dcs::wb_occupancy();
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
     if (dcs::error_slots(&c.err_slots) != hipSuccess || c.err_slots == nullptr) return DCS_EHIP;
@@ -444,6 +446,39 @@ struct BernLayout {
   size_t ctl = 0, tickets = 0, status = 0, total = 0;
 };
 
+// Whole-range Algorithm B: control block | state | chunk counts (u32) |
+// chunk offsets (u64) | removal counts per block of hit indices (u32) |
+// removal bitmap (u64 words).
+struct WbLayout {
+  size_t ctl = 0, state = 0, cnt = 0, off = 0, rem = 0, bitmap = 0, total = 0;
+};
+
+WbLayout wb_layout(uint64_t n_chunks, uint64_t rem_blocks, uint64_t words) {
+  WbLayout L;
+  size_t o = 0;
+  L.ctl = o;
+  o = align_up(o + sizeof(Control));
+  L.state = o;
+  o = align_up(o + sizeof(dcs::WbState));
+  L.cnt = o;
+  o = align_up(o + sizeof(uint32_t) * n_chunks);
+  L.off = o;
+  o = align_up(o + sizeof(uint64_t) * n_chunks);
+  L.rem = o;
+  o = align_up(o + sizeof(uint32_t) * rem_blocks);
+  L.bitmap = o;
+  o = align_up(o + sizeof(uint64_t) * words);
+  L.total = o;
+  return L;
+}
+
+uint64_t isqrt_host(uint64_t x) {
+  uint64_t r = static_cast<uint64_t>(sqrt(static_cast<double>(x)));
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
 BernLayout bern_layout(uint64_t n_chunks) {
   BernLayout L;
   size_t o = 0;
@@ -614,6 +649,63 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
   return run_tree_pipeline(c, ws, L, nullptr, static_cast<uint32_t>(K), tb, tt, leaf_cap,
                            stack_depth, out_dev, s, error_word(c, stream),
                            leaf_wgs_for(c, 0, n));
+}
+
+int32_t dcs_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, const dcs_params* params,
+                              uint64_t* out_dev, void* stream) {
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (N == 0 || N > (1ull << 32) || n > N || (n > 0 && out_dev == nullptr)) return DCS_EINVAL;
+  const uint64_t num = n + 8 * isqrt_host(n) + 16;
+  const int full = num >= N ? 1 : 0;
+  const double rho = full ? 1.0 : static_cast<double>(num) / static_cast<double>(N);
+  if (n > 0 && rho < 0x1p-10) return DCS_ENOTSUP;
+  if (n == 0) return DCS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  const uint64_t chunk = bern_chunk_len(rho, P.n0);
+  const uint64_t n_chunks = (N + chunk - 1) / chunk;
+  const uint64_t hi = n + 16 * isqrt_host(n) + 64;  // most hits an accepted attempt has
+  const uint64_t words = (hi + 63) / 64;
+  const uint64_t rem_blocks = (hi >> dcs::kWbRemShift) + 1;
+  const WbLayout L = wb_layout(n_chunks, rem_blocks, words);
+  void* ws = nullptr;
+  rc = own_workspace(c, L.total, &ws);
+  if (rc) return rc;
+  char* base = static_cast<char*>(ws);
+  Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
+  dcs::WbBuffers b;
+  b.state = reinterpret_cast<dcs::WbState*>(base + L.state);
+  b.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+  b.off = reinterpret_cast<uint64_t*>(base + L.off);
+  b.rem = reinterpret_cast<uint32_t*>(base + L.rem);
+  b.rem_blocks = rem_blocks;
+  b.bitmap = reinterpret_cast<unsigned long long*>(base + L.bitmap);
+  b.words = words;
+  const float c32 = full ? 0.0f : static_cast<float>(1.0 / host_log1p_series(-rho));
+  const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(
+      1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->wb_occupancy)));
+  hipError_t e = dcs::launch_wb_zero(ctl, b, n_chunks, error_word(c, stream), s);
+  // Two attempts are enqueued; the second one's kernels return at once when
+  // the first is accepted (a rejection has probability below about 1e-11).
+  for (uint32_t a = 0; a < 2 && e == hipSuccess; ++a) {
+    Timing t9{}, t10{}, t11{};
+    timing_begin(9, s, &t9);
+    e = dcs::launch_wb_count(N, seed, chunk, n_chunks, c32, full, a, b, grid, s);
+    timing_end(s, &t9);
+    if (e != hipSuccess) break;
+    timing_begin(10, s, &t10);
+    e = dcs::launch_wb_mid(n, seed, n_chunks, a, a == 1 ? 1 : 0, b, ctl, s);
+    timing_end(s, &t10);
+    if (e != hipSuccess) break;
+    timing_begin(11, s, &t11);
+    e = dcs::launch_wb_write(N, seed, chunk, n_chunks, c32, full, a, b, out_dev, grid, s);
+    timing_end(s, &t11);
+  }
+  return hip_status(e);
 }
 
 uint64_t dcs_bernoulli_capacity_hint(double p, uint64_t N) {

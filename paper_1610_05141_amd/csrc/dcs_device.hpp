@@ -35,6 +35,8 @@ enum Purpose : uint32_t {
   kWrLeaf = 7,   // with-replacement leaf: uniform offsets
   kSegSplit = 8, // uneven universe: split of a subtree of segments
   kSegSeed = 9,  // uneven universe: seed of one segment's own tree
+  kWChunk = 10,  // whole-range Algorithm B: skips of one chunk
+  kWRepair = 11, // whole-range Algorithm B: hits removed by the repair
 };
 
 constexpr uint64_t kMaxUniverse = 1ull << 52;

@@ -1821,6 +1821,229 @@ __global__ void k_bern_fill(uint64_t N, uint64_t* out, uint64_t capacity, uint64
 }
 
 // ---------------------------------------------------------------------------
+// Whole-range Algorithm B (Sec. 2's Algorithm B over all of 0..N-1 with the
+// skips and prefix sums of Sec. 4.7, as Sec. 5's GPU variant runs it, with
+// the removal of the excess hits done on the device instead of the host).
+// One attempt is three launches: a count pass (one wave per chunk, skips
+// only), one work-group that scans the chunk counts, decides acceptance,
+// draws the removed hit indices in rounds into a bitmap and scans the
+// per-chunk removal counts, and a write pass that recomputes each chunk and
+// writes its kept hits at their final places.
+// ---------------------------------------------------------------------------
+constexpr int kWbMidBlock = 1024;
+
+__global__ void k_wb_zero(Control* ctl, WbBuffers b, unsigned int* err) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < b.words; i += stride) b.bitmap[i] = 0;
+  for (uint64_t i = i0; i < b.rem_blocks; i += stride) b.rem[i] = 0;
+  if (i0 == 0) {
+    b.state->accepted = 0;
+    b.state->hits = 0;
+    start_control(ctl, err);
+  }
+}
+
+// Count pass: chunk j's hits counted 256 draws at a time exactly as
+// k_bern_wave counts them (chunks dealt statically, one wave each).
+__global__ __launch_bounds__(64) void k_wb_count(uint64_t N, uint64_t seed, uint64_t chunk,
+                                                 uint64_t n_chunks, float c32, int full,
+                                                 uint32_t attempt, WbBuffers b) {
+  if (b.state->accepted != 0) return;  // an earlier attempt was accepted
+  const uint32_t lane = lane_tid();
+  for (uint64_t j = blockIdx.x; j < n_chunks; j += gridDim.x) {
+    const uint64_t base = j * chunk;
+    const uint32_t len = static_cast<uint32_t>((N - base) < chunk ? (N - base) : chunk);
+    if (full) {
+      if (lane == 0) b.cnt[j] = len;
+      continue;
+    }
+    const Stream st = make_stream(seed, j, kWChunk, attempt);
+    uint32_t q_base = 0, cnt = 0;
+    for (uint32_t c = 0;; ++c) {
+      uint32_t inc[4];
+      const uint32_t sum = bern_group(st, c, lane, c32, inc);
+      const uint32_t incl = wave_scan_incl(sum);
+      uint32_t r = incl - sum, in = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        r += inc[k];
+        in += q_base + r <= len ? 1u : 0u;
+      }
+      const unsigned long long whole = __ballot(in == 4u);
+      const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+      const uint32_t got = nw == 64u ? kBernWaveGroup : 4u * nw + __builtin_amdgcn_readlane(in, nw);
+      cnt += got;
+      q_base += __builtin_amdgcn_readlane(incl, 63);
+      if (got < kBernWaveGroup) break;
+    }
+    if (lane == 0) b.cnt[j] = cnt;
+  }
+}
+
+// Exclusive prefix sums of x[0..count) into y (may be x), by one work-group
+// in tiles of 4 kWbMidBlock entries: thread t loads entries 4t..4t+3 of the
+// tile (coalesced), one block scan per tile, carry across tiles.  Returns
+// the total.
+template <typename TOut>
+__device__ uint64_t wg_scan_tiles(const uint32_t* x, TOut* y, uint64_t count, uint64_t* scr) {
+  constexpr uint64_t kTile = 4 * kWbMidBlock;
+  const uint32_t tid = threadIdx.x;
+  uint64_t carry = 0;
+  for (uint64_t t0 = 0; t0 < count; t0 += kTile) {
+    const uint64_t i = t0 + 4u * tid;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = i + k < count ? x[i + k] : 0u;
+    const uint64_t s = static_cast<uint64_t>(v[0]) + v[1] + v[2] + v[3];
+    uint64_t total;
+    uint64_t run = carry + block_scan_excl<kWbMidBlock, uint64_t>(s, scr, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k < count) y[i + k] = static_cast<TOut>(run);
+      run += v[k];
+    }
+    carry += total;
+  }
+  __syncthreads();
+  return carry;
+}
+
+// One work-group: hit offsets of the chunks (scan of the counts), the
+// acceptance test, and the repair.  The removed hit indices are the first
+// r = n' - n distinct non-void values of the (0, WREPAIR, attempt) words
+// mapped into [0, n'), found in rounds (each round takes as many more words
+// as values are missing; a word adds at most one new value, so the rounds
+// stop exactly where the sequential rule does); a value is new iff its
+// bitmap bit was clear, and then its block's removal count goes up.  Last,
+// the removal counts per block become their exclusive prefix.
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t seed,
+                                                        uint64_t n_chunks, uint32_t attempt,
+                                                        int last, WbBuffers b, Control* ctl) {
+  __shared__ uint64_t scr[kWbMidBlock / 64];
+  if (b.state->accepted != 0) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t hits = wg_scan_tiles(b.cnt, b.off, n_chunks, scr);
+  const uint64_t hi = n + 16 * isqrt64(n) + 64;
+  if (hits < n || hits > hi) {  // the same decision in every thread
+    if (last && tid == 0) atomicOr(ctl->err, kErrRestartLimit);
+    return;
+  }
+  const uint64_t r = hits - n;
+  if (r > 0) {
+    const Stream st = make_stream(seed, 0, kWRepair, attempt);
+    const uint32_t thr = range_threshold(hits);
+    uint64_t d = 0, t = 0;
+    while (d < r) {
+      const uint64_t t1 = t + (r - d);
+      uint64_t fresh = 0;
+      for (uint64_t blk = (t >> 2) + tid; (blk << 2) < t1; blk += kWbMidBlock) {
+        const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint64_t tk = (blk << 2) + k;
+          uint32_t v;
+          if (tk >= t && tk < t1 && range_map(pick(w, k), hits, thr, &v)) {
+            const unsigned long long bit = 1ull << (v & 63u);
+            const unsigned long long old = atomicOr(&b.bitmap[v >> 6], bit);
+            if ((old & bit) == 0) {
+              ++fresh;
+              atomicAdd(&b.rem[v >> kWbRemShift], 1u);
+            }
+          }
+        }
+      }
+      uint64_t total;
+      (void)block_scan_excl<kWbMidBlock, uint64_t>(fresh, scr, &total);
+      d += total;
+      t = t1;
+    }
+  }
+  __syncthreads();
+  (void)wg_scan_tiles(b.rem, b.rem, (hits + (1u << kWbRemShift) - 1) >> kWbRemShift, scr);
+  if (tid == 0) {
+    b.state->hits = hits;
+    b.state->accepted = attempt + 1;
+  }
+}
+
+// Write pass: chunk j again, group by group.  Its hits have global indices
+// off[j] .. ; the removals before its first hit are the prefix of its
+// index block plus the bitmap bits between the block's start and off[j]
+// (at most 2^kWbRemShift / 64 words).  Hit g, unless removed, goes to output
+// index g - (removals before g); a group's kept hits are staged in LDS in
+// order and stored with consecutive lanes on consecutive outputs.
+__global__ __launch_bounds__(64) void k_wb_write(uint64_t N, uint64_t seed, uint64_t chunk,
+                                                 uint64_t n_chunks, float c32, int full,
+                                                 uint32_t attempt, WbBuffers b, uint64_t* out) {
+  __shared__ uint64_t stage[kBernWaveGroup];
+  if (b.state->accepted != attempt + 1) return;  // not this attempt's sample
+  const uint32_t lane = lane_tid();
+  for (uint64_t j = blockIdx.x; j < n_chunks; j += gridDim.x) {
+    const uint64_t base = j * chunk;
+    const uint32_t len = static_cast<uint32_t>((N - base) < chunk ? (N - base) : chunk);
+    const uint64_t g0 = b.off[j];
+    // removals before g0: whole blocks, then the words of g0's block below g0
+    const uint64_t blk0 = g0 >> kWbRemShift;
+    uint64_t before = 0;
+    const uint64_t w_first = (blk0 << kWbRemShift) >> 6, w_end = g0 >> 6;  // words [w_first, w_end)
+    for (uint64_t w = w_first + lane; w < w_end; w += 64)
+      before += static_cast<uint64_t>(__popcll(b.bitmap[w]));
+    if (lane == 0 && (g0 & 63u) != 0)
+      before += static_cast<uint64_t>(__popcll(b.bitmap[w_end] & ~(~0ull << (g0 & 63u))));
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) before += __shfl_xor(before, d, 64);
+    before += b.state->hits > g0 ? b.rem[blk0] : 0u;
+    uint64_t o = g0 - before;  // output index of the chunk's next kept hit
+    const Stream st = make_stream(seed, j, kWChunk, attempt);
+    uint32_t q_base = 0;
+    for (uint32_t c = 0;; ++c) {
+      uint32_t inc[4] = {1u, 1u, 1u, 1u};
+      uint32_t sum = 4u;
+      if (!full) sum = bern_group(st, c, lane, c32, inc);
+      const uint32_t incl = wave_scan_incl(sum);
+      uint32_t rel[4];
+      uint32_t r = incl - sum, in = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        r += inc[k];
+        rel[k] = r;
+        in += q_base + r <= len ? 1u : 0u;
+      }
+      // removal bits of this lane's hits 256c + 4 lane + k (consecutive
+      // indices: at most two bitmap words)
+      const uint64_t gl = g0 + kBernWaveGroup * c + 4u * lane;
+      uint32_t keep = 0;
+      if (in > 0) {
+        const unsigned long long w0 = b.bitmap[gl >> 6];
+        const uint32_t sh = static_cast<uint32_t>(gl & 63u);
+        unsigned long long bits = w0 >> sh;
+        if (sh > 60u && in > 64u - sh) bits |= b.bitmap[(gl >> 6) + 1] << (64u - sh);
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+          if (k < in && ((bits >> k) & 1ull) == 0) keep |= 1u << k;
+      }
+      const uint32_t nk = static_cast<uint32_t>(__popc(keep));
+      const uint32_t kincl = wave_scan_incl(nk);
+      uint32_t slot = kincl - nk;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((keep >> k) & 1u) stage[slot++] = base + q_base + rel[k];
+      const uint32_t kept = __builtin_amdgcn_readlane(kincl, 63);
+#pragma unroll
+      for (uint32_t t = 0; t < 4; ++t) {
+        const uint32_t idx = 64u * t + lane;
+        if (idx < kept) store_out(out + o + idx, stage[idx]);
+      }
+      o += kept;
+      const unsigned long long whole = __ballot(in == 4u);
+      q_base += __builtin_amdgcn_readlane(incl, 63);
+      if (__popcll(whole) < 64) break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics kernel.
 // ---------------------------------------------------------------------------
 __global__ void k_debug(int op, const void* x, const void* x2, void* y, uint64_t count,
@@ -1993,6 +2216,52 @@ hipError_t launch_segments(Instance* inst, uint64_t K, uint32_t D, uint64_t n, u
   hipLaunchKernelGGL(k_segments, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
                      K, D, n, N, seed, counts);
   return hipGetLastError();
+}
+
+hipError_t launch_wb_zero(Control* ctl, const WbBuffers& b, uint64_t n_chunks, unsigned int* err,
+                          hipStream_t stream) {
+  (void)n_chunks;
+  const uint64_t most = b.words > b.rem_blocks ? b.words : b.rem_blocks;
+  uint64_t blocks = (most + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_wb_zero, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, b,
+                     err);
+  return hipGetLastError();
+}
+
+hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
+                           int full, uint32_t attempt, const WbBuffers& b, uint32_t grid,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_wb_count, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
+                     full, attempt, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
+                         const WbBuffers& b, Control* ctl, hipStream_t stream) {
+  hipLaunchKernelGGL(k_wb_mid, dim3(1), dim3(kWbMidBlock), 0, stream, n, seed, n_chunks, attempt,
+                     last, b, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_wb_write(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
+                           int full, uint32_t attempt, const WbBuffers& b, uint64_t* out,
+                           uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_wb_write, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
+                     full, attempt, b, out);
+  return hipGetLastError();
+}
+
+int wb_occupancy() {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &a, reinterpret_cast<const void*>(k_wb_count), 64, 0) != hipSuccess || a <= 0)
+    a = 8;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b, reinterpret_cast<const void*>(k_wb_write), 64, 0) != hipSuccess || b <= 0)
+    b = 8;
+  return a < b ? a : b;
 }
 
 hipError_t launch_bernoulli_fill(uint64_t N, uint64_t* out, uint64_t capacity, uint64_t* count_dev,

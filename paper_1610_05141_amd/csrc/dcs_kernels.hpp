@@ -87,6 +87,7 @@ constexpr unsigned kErrLeafCapacity = 1u;   // more leaves than the workspace ho
 constexpr unsigned kErrStackDepth = 2u;     // tree deeper than the planned stack
 constexpr unsigned kErrSpinLimit = 4u;      // Bernoulli look-back waited too long
 constexpr unsigned kErrLeafTooLarge = 8u;   // a leaf exceeds the kernel's LDS bound
+constexpr unsigned kErrRestartLimit = 16u;  // whole-range B: no attempt accepted
 
 constexpr uint64_t kMaxLeafJobs = 1ull << 31;  // keeps the two halves of leaf_counts apart
 constexpr int kLeafBlock = 512;             // threads of a leaf work-group
@@ -147,6 +148,43 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
 // depth D over them; counts (may be null) receives the K counts.
 hipError_t launch_segments(Instance* inst, uint64_t K, uint32_t D, uint64_t n, uint64_t N,
                            uint64_t seed, uint64_t* counts, hipStream_t stream);
+// Whole-range Algorithm B: the state word of a call (attempt + 1 once an
+// attempt is accepted, else 0) and its accepted hit count.
+struct WbState {
+  unsigned long long accepted;
+  unsigned long long hits;
+};
+// Removal counts are kept per block of 2^kWbRemShift hit indices.
+constexpr uint32_t kWbRemShift = 12;
+// Workspace of one call: per-chunk hit counts (u32) and their exclusive
+// prefix (u64); removal counts per block of hit indices (u32, turned into
+// their exclusive prefix); the removal bitmap over hit indices (u64 words).
+struct WbBuffers {
+  WbState* state;
+  uint32_t* cnt;
+  uint64_t* off;
+  uint32_t* rem;
+  uint64_t rem_blocks;
+  unsigned long long* bitmap;
+  uint64_t words;
+};
+// Zero the state, removal counts and bitmap; start the control block.
+hipError_t launch_wb_zero(Control* ctl, const WbBuffers& b, uint64_t n_chunks, unsigned int* err,
+                          hipStream_t stream);
+// Attempt `attempt`: count pass, then the one-work-group scan / acceptance /
+// repair, then the write pass (each returns at once if an earlier attempt
+// was accepted).  full: rho = 1 (every element a hit).  last: latch
+// kErrRestartLimit if this attempt is rejected too.
+hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
+                           int full, uint32_t attempt, const WbBuffers& b, uint32_t grid,
+                           hipStream_t stream);
+hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
+                         const WbBuffers& b, Control* ctl, hipStream_t stream);
+hipError_t launch_wb_write(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
+                           int full, uint32_t attempt, const WbBuffers& b, uint64_t* out,
+                           uint32_t grid, hipStream_t stream);
+// Resident one-wave work-groups per compute unit of the count and write passes.
+int wb_occupancy();
 hipError_t launch_bernoulli_fill(uint64_t N, uint64_t* out, uint64_t capacity,
                                  uint64_t* count_dev, hipStream_t stream);
 hipError_t launch_debug(int op, const void* x, const void* x2, void* y, uint64_t count,
