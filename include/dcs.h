@@ -392,8 +392,9 @@ const char* dcs_status_string(int32_t status);
  * kernel of the dense jobs with ranges up to 2^16, 7 = edge-index
  * decoding of the graph entry points, 8 = the segment splits of
  * dcs_sample_segments, 9 / 10 / 11 = the count passes / the scan and
- * repair / the write passes of dcs_sample_wholerange); DCS_EINVAL for
- * another kind. */
+ * repair / the write passes of dcs_sample_wholerange, 12 = one-wave-per-leaf
+ * kernel of the sparse and with-replacement jobs of at most 1024 values over
+ * ranges that are not powers of two); DCS_EINVAL for another kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 /* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind

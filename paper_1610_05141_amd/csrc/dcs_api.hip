@@ -218,8 +218,9 @@ void release_timings() {
 // 4 leaf kernel of the power-of-two list, 5 work-group leaf kernel of
 // the rest, 6 one-wave dense leaf kernel, 7 edge-index decoding, 8 splits
 // of the segments of an uneven universe, 9 / 10 / 11 whole-range
-// Algorithm B: count passes / scan and repair / write passes
-constexpr int kProfKinds = 12;
+// Algorithm B: count passes / scan and repair / write passes, 12 one-wave
+// leaf kernel of the small sparse and with-replacement leaves
+constexpr int kProfKinds = 13;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 
@@ -237,6 +238,7 @@ int32_t device_ctx(DeviceCtx** out) {
     c.leaf_occupancy = dcs::leaf_occupancy();
     c.bern_wave_occupancy = dcs::bern_wave_occupancy();
     c.wb_occupancy = dcs::wb_occupancy();
+    c.small_occupancy = dcs::small_occupancy();
     c.dense_occupancy = dcs::dense_occupancy();
     if (const char* e = getenv("DCS_LEAF_GRID")) c.leaf_grid = atoll(e);
     if (dcs::error_slots(&c.err_slots) != hipSuccess || c.err_slots == nullptr) return DCS_EHIP;
@@ -389,6 +391,15 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
     timing_begin(6, s, &t6);
     e = dcs::launch_leaf_dense(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(waves), s);
     timing_end(s, &t6);
+  }
+  Timing t12{};
+  if (e == hipSuccess) {
+    uint64_t waves = static_cast<uint64_t>(c->cus) * std::max(1, c->small_occupancy);
+    if (c->leaf_grid > 0) waves = static_cast<uint64_t>(c->leaf_grid) * (dcs::kLeafBlock / 64);
+    waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, leaf_cap));
+    timing_begin(12, s, &t12);
+    e = dcs::launch_leaf_small(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(waves), s);
+    timing_end(s, &t12);
   }
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;

@@ -48,6 +48,7 @@ struct DeviceCtx {
   int bern_wave_occupancy = 8;
   int dense_occupancy = 8;
   int wb_occupancy = 8;
+  int small_occupancy = 8;
   // launch-geometry overrides (never change the sample): DCS_LEAF_GRID sets
   // the number of leaf work-groups, DCS_CUT_BIAS shifts the Algorithm P cut;
   // when set they take precedence over the tuning table

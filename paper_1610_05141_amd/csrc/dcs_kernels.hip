@@ -1072,6 +1072,224 @@ __device__ void leaf_dense_wave(const Leaf& L, uint64_t* out, uint16_t* list, ui
 }
 
 // Constant leaf of a with-replacement tree: N_v = 1, every draw is lo+1.
+// ---------------------------------------------------------------------------
+// Small sparse and with-replacement leaves, one wave per leaf.
+// ---------------------------------------------------------------------------
+// Sparse and with-replacement leaves of the back list (ranges that are not
+// powers of two) with at most kSmallMax values are taken by k_leaf_small,
+// one wave each with no barrier: the same values as leaf_sparse / leaf_wr
+// (the first n_v non-void values of the leaf's stream, for a sparse leaf
+// Algorithm H's distinct ones by rounds), ranked in stream order by wave
+// scans, sorted by a counting pass over kSmallBuckets buckets and the
+// Batcher windows, and written with consecutive lanes on consecutive
+// outputs.  The work-group leaf loop skips them.
+constexpr uint32_t kSmallKpl = 16;                     // keys per lane
+constexpr uint32_t kSmallMax = 64 * kSmallKpl;         // 1024 values
+constexpr uint32_t kSmallBucketBits = 10;
+constexpr uint32_t kSmallBuckets = 1u << kSmallBucketBits;
+static_assert(kSmallBuckets == kSmallMax, "one bucket per key slot");
+// counter of bucket b at spad(b): one pad word per 16, so that lane l's
+// run of 16 counters (words 17 l .. 17 l + 15) spans 16 distinct banks
+__device__ __forceinline__ uint32_t spad(uint32_t b) { return b + (b >> 4); }
+constexpr uint32_t kSmallCnt = kSmallBuckets + kSmallBuckets / 16;
+constexpr uint32_t kSmallKeys = kSmallMax + 32;        // keys, then sentinels
+
+__device__ __forceinline__ bool small_by_wave(const Leaf& L) {
+  const uint32_t kind = L.flags & 3u;
+  return (kind == kKindSparse || kind == kKindWr) && L.nv <= kSmallMax;
+}
+
+// The first `need` non-void values in [0, s) of the 32-bit stream from word
+// t0 on, in stream order, into dst[0..need), by one wave: lane l maps the
+// words of Philox block (t >> 2) + l, a wave scan ranks the non-void ones.
+// Returns the word index just after the last value taken.
+__device__ uint64_t take_wave(const Stream& st, uint64_t t0, uint32_t need, const RangeInfo& ri,
+                              uint32_t* dst, uint32_t lane) {
+  uint32_t done = 0;
+  uint64_t t = t0, after = t0;
+  while (done < need) {
+    const uint64_t blk = (t >> 2) + lane;
+    const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
+    uint32_t v[4], ok = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bool good = true;
+      if (ri.pow2)
+        v[j] = ri.pshift >= 32 ? 0u : (pick(w, j) >> ri.pshift);
+      else
+        good = range_map(pick(w, j), ri.s, ri.thr, &v[j]);
+      if (good && 4 * blk + j >= t) ok |= 1u << j;
+    }
+    const uint32_t c = static_cast<uint32_t>(__popc(ok));
+    const uint32_t incl = wave_scan_incl(c);
+    uint32_t p = done + incl - c;
+    bool has_last = false;
+    uint64_t last = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if ((ok >> j) & 1u) {
+        if (p < need) dst[p] = v[j];
+        if (p == need - 1) {
+          has_last = true;
+          last = 4 * blk + j + 1;
+        }
+        ++p;
+      }
+    }
+    const unsigned long long m = __ballot(has_last);
+    if (m != 0) {
+      const uint32_t f = static_cast<uint32_t>(__ffsll(static_cast<long long>(m)) - 1);
+      after = static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(last), f)) |
+              (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(last >> 32), f))
+               << 32);
+    }
+    done += __builtin_amdgcn_readlane(incl, 63);
+    t = ((t >> 2) + 64) << 2;
+  }
+  return after;
+}
+
+// W-key windows at off + W i of keys[0..n) (sentinels follow n); merge: each
+// window's halves are already sorted.  True iff some window holds equal
+// neighbours below n.
+template <int W, bool kMerge>
+__device__ __forceinline__ bool wave_windows(uint32_t* keys, uint32_t n, uint32_t off,
+                                             uint32_t lane) {
+  bool dup = false;
+  for (uint32_t w0 = off + W * lane; w0 < n; w0 += 64 * W) {
+    uint4* p = reinterpret_cast<uint4*>(keys + w0);
+    uint32_t v[W];
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q) {
+      const uint4 x = p[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+    sort_net<W, kMerge>(v);
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q)
+      p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    const uint32_t lim = n - w0;
+#pragma unroll
+    for (int i = 0; i + 1 < W; ++i)
+      dup = dup || (v[i] == v[i + 1] && static_cast<uint32_t>(i + 1) < lim);
+  }
+  return __ballot(dup) != 0;
+}
+
+// keys[0..n) ascending by one wave (n <= kSmallMax, keys >> shift below
+// kSmallBuckets); returns true iff a value repeats.  Counting pass by
+// key >> shift (LDS atomics give each key its slot in its bucket), scan of
+// the counts (lane l owns buckets 16 l .. 16 l + 15), scatter back into
+// keys, then the Batcher windows of the work-group sort (8-key windows and
+// merge windows shifted by 4 when no bucket holds more than 5 keys, 16-key
+// ones up to 9), else odd-even transposition rounds.
+__device__ bool wave_sort(uint32_t* keys, uint32_t n, uint32_t shift, uint32_t* cnt,
+                          uint32_t lane) {
+  for (uint32_t w = lane; w < kSmallCnt / 4; w += 64)
+    reinterpret_cast<uint4*>(cnt)[w] = make_uint4(0, 0, 0, 0);
+  uint32_t kk[kSmallKpl], as[kSmallKpl];
+#pragma unroll
+  for (uint32_t q = 0; q < kSmallKpl; ++q) {
+    const uint32_t i = 64 * q + lane;
+    kk[q] = 0;
+    as[q] = ~0u;
+    if (i < n) {
+      kk[q] = keys[i];
+      const uint32_t b = spad(kk[q] >> shift);
+      as[q] = b | (atomicAdd(&cnt[b], 1u) << 16);
+    }
+  }
+  {
+    uint32_t* run = cnt + spad(kSmallKpl * lane);
+    uint32_t c[kSmallKpl];
+    uint32_t sum = 0, big = 0;
+#pragma unroll
+    for (uint32_t m = 0; m < kSmallKpl; ++m) {
+      c[m] = run[m];
+      sum += c[m];
+      big = max(big, c[m]);
+    }
+    const uint32_t incl = wave_scan_incl(sum);
+    uint32_t acc = incl - sum;
+#pragma unroll
+    for (uint32_t m = 0; m < kSmallKpl; ++m) {
+      run[m] = acc;
+      acc += c[m];
+    }
+    big = __builtin_amdgcn_readlane(wave_max_incl(big), 63);
+    if (lane < 24) keys[n + lane] = 0xFFFFFFFFu;
+#pragma unroll
+    for (uint32_t q = 0; q < kSmallKpl; ++q)
+      if (as[q] != ~0u) keys[cnt[as[q] & 0xFFFFu] + (as[q] >> 16)] = kk[q];
+    if (shift == 0 || big <= 1) return shift == 0 && big >= 2;
+    if (big <= 5) {
+      const bool d = wave_windows<8, false>(keys, n, 0, lane);
+      return wave_windows<8, true>(keys, n, 4, lane) || d;
+    }
+    if (big <= 9) {
+      const bool d = wave_windows<16, false>(keys, n, 0, lane);
+      return wave_windows<16, true>(keys, n, 8, lane) || d;
+    }
+    for (uint32_t r = 0; r < big; ++r) {
+      for (uint32_t i = 2 * lane + (r & 1u); i + 1 < n; i += 128) {
+        const uint32_t a = keys[i], b = keys[i + 1];
+        keys[i] = min(a, b);
+        keys[i + 1] = max(a, b);
+      }
+    }
+  }
+  bool dup = false;
+  for (uint32_t i = lane; i + 1 < n; i += 64) dup = dup || keys[i] == keys[i + 1];
+  return __ballot(dup) != 0;
+}
+
+// keys[0..n) ascending with equal values adjacent -> the distinct values in
+// keys[0..d); returns d (one wave; every key is read before any is moved).
+__device__ uint32_t compact_wave(uint32_t* keys, uint32_t n, uint32_t lane) {
+  uint32_t kk[kSmallKpl];
+  uint32_t keep = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kSmallKpl; ++q) {
+    const uint32_t i = 64 * q + lane;
+    kk[q] = 0;
+    if (i < n) {
+      kk[q] = keys[i];
+      if (i == 0 || keys[i - 1] != kk[q]) keep |= 1u << q;
+    }
+  }
+  uint32_t d = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kSmallKpl; ++q) {
+    const unsigned long long m = __ballot((keep >> q) & 1u);
+    if ((keep >> q) & 1u) keys[d + lane_rank(m)] = kk[q];
+    d += static_cast<uint32_t>(__popcll(m));
+  }
+  return d;
+}
+
+__device__ void leaf_small_wave(const Leaf& L, uint64_t* out, uint32_t* keys, uint32_t* cnt) {
+  const uint32_t lane = lane_tid();
+  const uint32_t nv = L.nv;
+  const bool wr = (L.flags & 3u) == kKindWr;
+  const RangeInfo ri = range_info(L.Nv);
+  const uint32_t kb = bit_length(L.Nv - 1);
+  const uint32_t shift = kb > kSmallBucketBits ? kb - kSmallBucketBits : 0u;
+  const Stream st = make_stream(L.seed, L.id, wr ? kWrLeaf : kLeaf, 0);
+  uint64_t t = take_wave(st, 0, nv, ri, keys, lane);
+  bool dups = wave_sort(keys, nv, shift, cnt, lane);
+  while (dups && !wr) {  // Algorithm H's rounds (sparse leaves only)
+    const uint32_t have = compact_wave(keys, nv, lane);
+    t = take_wave(st, t, nv - have, ri, keys + have, lane);
+    dups = wave_sort(keys, nv, shift, cnt, lane);
+  }
+  const uint64_t b1 = L.lo + 1;
+  uint64_t* o = out + L.off;
+  for (uint32_t i = lane; i < nv; i += 64) store_out(o + i, b1 + keys[i]);
+}
+
 template <int B>
 __device__ void leaf_fill(const Leaf& L, uint64_t* out) {
   uint64_t* o = out + L.off;
@@ -1139,8 +1357,9 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
             Leaf c;
             const uint32_t* r = cache + tid * kLeafWords;
             c.Nv = static_cast<uint64_t>(r[4]) | (static_cast<uint64_t>(r[5]) << 32);
+            c.nv = r[10];
             c.flags = r[11];
-            run = !dense_by_wave(c);
+            run = !dense_by_wave(c) && !small_by_wave(c);
           }
           const unsigned long long m = __ballot(run);
           if (tid == 0) sm.scr[kScrKeep] = static_cast<uint32_t>(m);
@@ -1153,7 +1372,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
         }
       }
     }
-    if (!kPow2 && !((keep >> slot) & 1u)) continue;  // k_leaf_dense's
+    if (!kPow2 && !((keep >> slot) & 1u)) continue;  // a one-wave kernel's
     Leaf L;
     {
       const uint4* c = reinterpret_cast<const uint4*>(cache + slot * kLeafWords);
@@ -1227,6 +1446,30 @@ __global__ __launch_bounds__(64) void k_leaf_dense(const Leaf* __restrict__ leav
     L.flags = __builtin_amdgcn_readfirstlane(rec->flags);
     if (!dense_by_wave(L) || L.nv == 0) continue;
     leaf_dense_wave(L, out, list, mask, bases);
+  }
+}
+
+// Small sparse and with-replacement leaves of the back list, one wave (and
+// work-group) per leaf: back job i goes to wave i mod G.
+__global__ __launch_bounds__(64) void k_leaf_small(const Leaf* __restrict__ leaves,
+                                                   uint64_t leaf_cap, uint64_t* out, Control* ctl) {
+  __shared__ __align__(16) uint32_t keys[kSmallKeys];
+  __shared__ __align__(16) uint32_t cnt[kSmallCnt];
+  const uint64_t counts = uniform64(ctl->leaf_counts);
+  const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
+  if (front + back > leaf_cap) return;  // reported by k_leaf_mixed
+  for (uint64_t i = blockIdx.x; i < back; i += gridDim.x) {
+    const Leaf* rec = leaves + (leaf_cap - 1 - i);
+    Leaf L;
+    L.nv = __builtin_amdgcn_readfirstlane(rec->nv);
+    L.flags = __builtin_amdgcn_readfirstlane(rec->flags);
+    if (!small_by_wave(L) || L.nv == 0) continue;
+    L.id = uniform64(rec->id);
+    L.lo = uniform64(rec->lo);
+    L.Nv = uniform64(rec->Nv);
+    L.off = uniform64(rec->off);
+    L.seed = uniform64(rec->seed);
+    leaf_small_wave(L, out, keys, cnt);
   }
 }
 
@@ -2125,6 +2368,21 @@ int leaf_occupancy() {
       occ <= 0)
     occ = 2;
   return occ;
+}
+
+int small_occupancy() {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_leaf_small), 64, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 8;
+  return occ;
+}
+
+hipError_t launch_leaf_small(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                             uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_leaf_small, dim3(grid), dim3(64), 0, stream, leaves, leaf_cap, out, ctl);
+  return hipGetLastError();
 }
 
 int dense_occupancy() {

@@ -115,6 +115,8 @@ hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
 int leaf_occupancy();
 // Resident k_leaf_dense work-groups (one wave each) per compute unit.
 int dense_occupancy();
+// Resident k_leaf_small work-groups (one wave each) per compute unit.
+int small_occupancy();
 // Resident work-groups per compute unit of the double-precision Bernoulli
 // kernel holding lds_cap offsets in LDS, and of the one-wave
 // single-precision one.
@@ -137,6 +139,10 @@ hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, ui
 // Dense leaves of the back list whose range fits 16-bit positions, one wave
 // per leaf (k_leaf_mixed skips them).
 hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                             uint32_t grid, hipStream_t stream);
+// Sparse and with-replacement leaves of the back list with at most 1024
+// values, one wave per leaf (k_leaf_mixed skips them).
+hipError_t launch_leaf_small(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
                              uint32_t grid, hipStream_t stream);
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
