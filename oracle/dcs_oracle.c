@@ -53,8 +53,15 @@
 /* ------------------------------------------------------------------------ */
 enum { REF_OK = 0, REF_EINVAL = 1, REF_ENOMEM = 2, REF_EOVERFLOW = 4 };
 
-/* Largest universe accepted: keeps every integer that enters a double exact. */
+/* Largest universe of Bernoulli sampling: chunk positions and their counts
+ * stay exact in a double, and the look-back words stay few. */
 #define REF_MAX_N (1ULL << 52)
+/* Largest universe of the recursion tree (without and with replacement,
+ * parts, segments, G(n, m)): node ids and output values stay below 2^63;
+ * integers above 2^53 enter the hypergeometric deviate's doubles rounded,
+ * which only perturbs its ratio-of-uniforms test at the level of the
+ * rounding of its logarithms (the mode and the exact cases stay integer). */
+#define REF_MAX_TREE_N (1ULL << 62)
 /* A leaf's range must fit a 32-bit draw. */
 #define REF_LEAF_MAX_RANGE (1ULL << 32)
 
@@ -705,7 +712,7 @@ EXPORT int dcs_ref_sample_window(uint64_t n, uint64_t N, uint64_t seed, uint32_t
                                  uint32_t dense_ratio, uint64_t start, uint64_t count,
                                  uint64_t *out) {
   if (check_params(n0, dense_ratio) != REF_OK) return REF_EINVAL;
-  if (N > REF_MAX_N || n > N) return REF_EINVAL;
+  if (N > REF_MAX_TREE_N || n > N) return REF_EINVAL;
   if (count > 0 && (out == NULL || start > n || count > n - start)) return REF_EINVAL;
   if (count == 0) return REF_OK;
   ctx_t c = {seed, n0, dense_ratio};
@@ -721,7 +728,7 @@ EXPORT int dcs_ref_sample(uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
 EXPORT int dcs_ref_replacement_window(uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
                                       uint64_t start, uint64_t count, uint64_t *out) {
   if (n0 < 2 || n0 > 4096) return REF_EINVAL;
-  if (N > REF_MAX_N || (N == 0 && n > 0)) return REF_EINVAL;
+  if (N > REF_MAX_TREE_N || (N == 0 && n > 0)) return REF_EINVAL;
   if (count > 0 && (out == NULL || start > n || count > n - start)) return REF_EINVAL;
   if (count == 0) return REF_OK;
   ctx_t c = {seed, n0, 16};
@@ -751,7 +758,7 @@ EXPORT int dcs_ref_part(int variant, uint64_t n, uint64_t N, uint64_t seed, uint
   *count = 0;
   *rank = 0;
   if (variant != 0 && variant != 1) return REF_EINVAL;
-  if (check_params(n0, dense_ratio) != REF_OK || N > REF_MAX_N) return REF_EINVAL;
+  if (check_params(n0, dense_ratio) != REF_OK || N > REF_MAX_TREE_N) return REF_EINVAL;
   if (variant == 0 && n > N) return REF_EINVAL;
   if (variant == 1 && N == 0 && n > 0) return REF_EINVAL;
   if (depth > 45 || index >= (1ULL << depth)) return REF_EINVAL;
@@ -799,16 +806,26 @@ EXPORT int dcs_ref_part(int variant, uint64_t n, uint64_t N, uint64_t seed, uint
  * (0-based) is the pair (u, v), v < u, with k = u(u-1)/2 + v, i.e. u is the
  * unique integer with u(u-1)/2 <= k < u(u+1)/2.  Since 8k+1 then lies in
  * [(2u-1)^2, (2u+1)^2), u = (1 + isqrt(8k+1)) / 2 (integer square root). */
+/* floor(sqrt(x)) of a 128-bit integer: a double estimate, then exact
+ * integer corrections. */
+static uint64_t isqrt_u128(unsigned __int128 x) {
+  uint64_t r = (uint64_t)sqrt((double)x);
+  while ((unsigned __int128)r * r > x) --r;
+  while ((unsigned __int128)(r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
 static void edge_pair(uint64_t k, uint64_t *u, uint64_t *v) {
-  uint64_t r = isqrt_u64(8 * k + 1);
+  uint64_t r = isqrt_u128(8 * (unsigned __int128)k + 1);
   *u = (1 + r) / 2;
   *v = k - *u * (*u - 1) / 2;
 }
 
-static int edge_count(uint64_t n_vertices, uint64_t *N) {
+/* max_N: the largest universe of the sampler the graph uses. */
+static int edge_count(uint64_t n_vertices, uint64_t max_N, uint64_t *N) {
   if (n_vertices > (1ULL << 32)) return REF_EINVAL;
   *N = n_vertices < 2 ? 0 : n_vertices * (n_vertices - 1) / 2;
-  return *N > REF_MAX_N ? REF_EINVAL : REF_OK;
+  return *N > max_N ? REF_EINVAL : REF_OK;
 }
 
 static void decode_edges(const uint64_t *vals, uint64_t count, uint32_t *uv) {
@@ -825,7 +842,7 @@ EXPORT void dcs_ref_edge_pair(uint64_t k, uint64_t out[2]) { edge_pair(k, &out[0
 EXPORT int dcs_ref_edges_gnm(uint64_t n_vertices, uint64_t m, uint64_t seed, uint32_t n0,
                              uint32_t *uv) {
   uint64_t N;
-  if (edge_count(n_vertices, &N) != REF_OK || m > N) return REF_EINVAL;
+  if (edge_count(n_vertices, REF_MAX_TREE_N, &N) != REF_OK || m > N) return REF_EINVAL;
   if (m == 0) return REF_OK;
   uint64_t *vals = (uint64_t *)malloc(m * sizeof(uint64_t));
   if (!vals) return REF_ENOMEM;
@@ -843,7 +860,7 @@ EXPORT int dcs_ref_edges_gnp(uint64_t n_vertices, double p, uint64_t seed, uint3
   uint64_t N;
   if (count == NULL) return REF_EINVAL;
   *count = 0;
-  if (edge_count(n_vertices, &N) != REF_OK) return REF_EINVAL;
+  if (edge_count(n_vertices, REF_MAX_N, &N) != REF_OK) return REF_EINVAL;
   uint64_t *vals = (uint64_t *)malloc((capacity ? capacity : 1) * sizeof(uint64_t));
   if (!vals) return REF_ENOMEM;
   int rc = dcs_ref_bernoulli(p, N, seed, n0, vals, capacity, count);
@@ -976,7 +993,7 @@ static int segments_check(uint64_t n, const uint64_t *lengths, uint64_t K, uint6
   if (K == 0 || K > REF_MAX_SEGMENTS || lengths == NULL) return REF_EINVAL;
   uint64_t total = 0;
   for (uint64_t i = 0; i < K; ++i) {
-    if (lengths[i] > REF_MAX_N - total) return REF_EINVAL;
+    if (lengths[i] > REF_MAX_TREE_N - total) return REF_EINVAL;
     total += lengths[i];
   }
   if (n > total) return REF_EINVAL;
@@ -1186,7 +1203,7 @@ static void count_nodes(const ctx_t *c, uint64_t id, uint64_t Nv, uint64_t nv,
 
 EXPORT int dcs_ref_tree_stats(uint64_t n, uint64_t N, uint64_t seed, uint32_t n0,
                               uint64_t stats[3]) {
-  if (n0 < 2 || n0 > 4096 || N > REF_MAX_N || n > N) return REF_EINVAL;
+  if (n0 < 2 || n0 > 4096 || N > REF_MAX_TREE_N || n > N) return REF_EINVAL;
   ctx_t c = {seed, n0, 16};
   stats[0] = stats[1] = stats[2] = 0;
   count_nodes(&c, 1, N, n, &stats[0], &stats[1], &stats[2], 0);

@@ -58,7 +58,7 @@ def test_degenerate_samples(ref):
     with pytest.raises(RuntimeError):
         ref.sample(11, 10, 1)
     with pytest.raises(RuntimeError):
-        ref.sample(1, 2**52 + 1, 1)
+        ref.sample(1, 2**62 + 1, 1)
     with pytest.raises(RuntimeError):
         ref.sample(1, 10, 1, n0=1)
 

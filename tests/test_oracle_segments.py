@@ -172,6 +172,6 @@ def test_degenerate_cases():
     v, c = oracle.sample_segments(7, [0, 0, 0, 100, 0, 0, 0, 0], 4, n0=2)
     assert c.tolist() == [0, 0, 0, 7, 0, 0, 0, 0]
     assert np.all((v >= 1) & (v <= 100)) and np.all(np.diff(v.astype(np.int64)) > 0)
-    for bad in [(3, [], 1), (10, [4, 5], 1), (1, [1 << 52, 1], 1)]:
+    for bad in [(3, [], 1), (10, [4, 5], 1), (1, [1 << 62, 1], 1)]:
         with pytest.raises(RuntimeError):
             oracle.sample_segments(*bad)
