@@ -365,10 +365,15 @@ def bench_graph(dcs, reps: int = 5):
     cap = dcs.bernoulli_capacity_hint(p, N)
     eg = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    # G(n, m) on 2^30 vertices: about 2^59 pairs, beyond 2^53
+    n_big, m_big = 1 << 30, 1 << 24
     cases = {
         "gnm": (lambda: dcs.sample_edges_gnm(n, m, seed, out=e, stream=stream), None),
         "gnp": (lambda: dcs.sample_edges_gnp(n, p, seed, out=eg, capacity=cap, count=cnt,
                                              stream=stream), cnt),
+        "gnm_2^30_vertices_2^24_edges": (
+            lambda: dcs.sample_edges_gnm(n_big, m_big, seed, out=e[:m_big], stream=stream),
+            m_big),
     }
     for name, (run, count) in cases.items():
         run()
@@ -381,7 +386,7 @@ def bench_graph(dcs, reps: int = 5):
         dt = (time.perf_counter() - t0) / reps
         d_ms, d_n = dcs.profile_read(7)
         dcs.profile_enable(False)
-        edges = m if count is None else int(count.item())
+        edges = m if count is None else (count if isinstance(count, int) else int(count.item()))
         dec = d_ms / max(d_n, 1)
         res[name] = {
             "edges": edges,

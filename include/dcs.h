@@ -49,8 +49,14 @@ typedef enum dcs_status {
   DCS_ENOTSUP = 6    /* request outside what the library supports */
 } dcs_status;
 
-/* Largest universe N accepted (every integer entering a double stays exact). */
-#define DCS_MAX_UNIVERSE (1ull << 52)
+/* Largest universe N of the recursion tree (samples without and with
+ * replacement, parts, batches, served requests, segments, G(n, m)): node ids
+ * and values stay below 2^63, the split's mode and exact cases are integer
+ * computations; integers above 2^53 enter the deviates' doubles rounded. */
+#define DCS_MAX_UNIVERSE (1ull << 62)
+/* Largest universe of Bernoulli sampling and G(n, p) (chunk positions stay
+ * exact in doubles). */
+#define DCS_MAX_BERNOULLI_UNIVERSE (1ull << 52)
 
 /* Canonical parameters: part of the sample's identity (changing one changes
  * the sample).  Pass NULL for the defaults. */
@@ -123,7 +129,7 @@ int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed,
  *   out_dev:   capacity uint64 slots; the first min(count, capacity) values
  *              are written.
  *   count_dev: one uint64 in device memory, receives the true count.
- * Errors: DCS_EINVAL if p is NaN or outside [0,1], N > DCS_MAX_UNIVERSE, or
+ * Errors: DCS_EINVAL if p is NaN or outside [0,1], N > DCS_MAX_BERNOULLI_UNIVERSE, or
  * a NULL pointer where one is needed.  A count above `capacity` is not an
  * error of the call (it cannot be known when the call returns): compare
  * *count_dev with capacity after synchronizing; re-running with a larger
@@ -189,7 +195,7 @@ int32_t dcs_sample_edges_gnm(uint64_t n_vertices, uint64_t m, uint64_t seed,
  *              (compare with capacity after synchronizing, as for
  *              dcs_sample_bernoulli).
  * Errors: as dcs_sample_bernoulli, plus DCS_EINVAL if n(n-1)/2 >
- * DCS_MAX_UNIVERSE or uv_dev is not 8-byte aligned.
+ * DCS_MAX_BERNOULLI_UNIVERSE or uv_dev is not 8-byte aligned.
  */
 int32_t dcs_sample_edges_gnp(uint64_t n_vertices, double p, uint64_t seed,
                              const dcs_params* params, uint32_t* uv_dev, uint64_t capacity,

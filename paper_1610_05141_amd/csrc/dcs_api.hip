@@ -733,7 +733,7 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
                                 void* workspace, size_t ws_bytes, void* stream) {
   Params P;
   if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
-  if (!(p >= 0.0 && p <= 1.0) || N > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (!(p >= 0.0 && p <= 1.0) || N > DCS_MAX_BERNOULLI_UNIVERSE) return DCS_EINVAL;
   if (count_dev == nullptr || (capacity > 0 && out_dev == nullptr)) return DCS_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -811,7 +811,7 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
   }
   if (variant == 2) {
     const double p = p_for_bernoulli;
-    if (!(p >= 0.0 && p <= 1.0)) return DCS_EINVAL;
+    if (!(p >= 0.0 && p <= 1.0) || N > DCS_MAX_BERNOULLI_UNIVERSE) return DCS_EINVAL;
     if (p == 0.0 || p == 1.0 || N == 0) {
       *bytes = align_up(sizeof(Control));
       return DCS_OK;

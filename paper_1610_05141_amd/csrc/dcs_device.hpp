@@ -39,7 +39,6 @@ enum Purpose : uint32_t {
   kWRepair = 11, // whole-range Algorithm B: hits removed by the repair
 };
 
-constexpr uint64_t kMaxUniverse = 1ull << 52;
 constexpr uint64_t kLeafMaxRange = 1ull << 32;
 
 // ---------------------------------------------------------------------------

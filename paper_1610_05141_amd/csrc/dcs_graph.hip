@@ -19,16 +19,17 @@
 
 namespace dcs {
 
-// Pair (u, v) of edge index k < 2^52: u is the integer with
+// Pair (u, v) of edge index k < 2^62: u is the integer with
 // u(u-1)/2 <= k < u(u+1)/2, i.e. the floor of (1 + sqrt(8k+1))/2.  The FP64
-// root (8k+1 < 2^55, relative error near 2^-53) puts the floor within one
-// of u, and at most one step of integer comparison against the triangular
-// numbers (products below 2^55) each way makes it exact; two are allowed.
-// An index outside that range (no sample value produces one) gives the
-// pair (2^32-1, 2^32-1) instead of an unbounded correction.
+// root of 8k+1 (formed in double, below 2^65; relative error near 2^-52)
+// puts the floor within one of u (u < 2^32), and at most one step of
+// integer comparison against the triangular numbers (products below 2^64)
+// each way makes it exact; two are allowed.  An index outside that range
+// (no sample value produces one) gives the pair (2^32-1, 2^32-1) instead of
+// an unbounded correction.
 __device__ __forceinline__ uint64_t edge_pair(uint64_t k) {
-  if (k >= (1ull << 52)) return ~0ull;
-  const double r = sqrt(static_cast<double>(8 * k + 1));
+  if (k >= (1ull << 62)) return ~0ull;
+  const double r = sqrt(8.0 * static_cast<double>(k) + 1.0);
   uint64_t u = static_cast<uint64_t>((1.0 + r) * 0.5);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -61,11 +62,11 @@ namespace {
 using namespace dcs::host;
 
 // Edges of a graph on n vertices, or an error if n(n-1)/2 exceeds the
-// largest universe.
-int32_t edge_universe(uint64_t n_vertices, uint64_t* N) {
+// largest universe of the sampler used (max_N).
+int32_t edge_universe(uint64_t n_vertices, uint64_t max_N, uint64_t* N) {
   if (n_vertices > (1ull << 32)) return DCS_EINVAL;
   const uint64_t e = n_vertices < 2 ? 0 : n_vertices * (n_vertices - 1) / 2;
-  if (e > DCS_MAX_UNIVERSE) return DCS_EINVAL;
+  if (e > max_N) return DCS_EINVAL;
   *N = e;
   return DCS_OK;
 }
@@ -94,7 +95,7 @@ extern "C" {
 int32_t dcs_sample_edges_gnm(uint64_t n_vertices, uint64_t m, uint64_t seed,
                              const dcs_params* params, uint32_t* uv_dev, void* stream) {
   uint64_t N = 0;
-  if (edge_universe(n_vertices, &N) != DCS_OK || m > N) return DCS_EINVAL;
+  if (edge_universe(n_vertices, DCS_MAX_UNIVERSE, &N) != DCS_OK || m > N) return DCS_EINVAL;
   if (m > 0 && (uv_dev == nullptr || (reinterpret_cast<uintptr_t>(uv_dev) & 7u) != 0))
     return DCS_EINVAL;
   if (m == 0) return DCS_OK;
@@ -108,7 +109,7 @@ int32_t dcs_sample_edges_gnp(uint64_t n_vertices, double p, uint64_t seed,
                              const dcs_params* params, uint32_t* uv_dev, uint64_t capacity,
                              uint64_t* count_dev, void* stream) {
   uint64_t N = 0;
-  if (edge_universe(n_vertices, &N) != DCS_OK) return DCS_EINVAL;
+  if (edge_universe(n_vertices, DCS_MAX_BERNOULLI_UNIVERSE, &N) != DCS_OK) return DCS_EINVAL;
   if (capacity > 0 && (uv_dev == nullptr || (reinterpret_cast<uintptr_t>(uv_dev) & 7u) != 0))
     return DCS_EINVAL;
   uint64_t* x = reinterpret_cast<uint64_t*>(uv_dev);

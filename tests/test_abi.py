@@ -57,7 +57,7 @@ def test_sample_part_rejects_bad_arguments_before_any_device_call():
         (2, 10, 100, 1, 0, 0, out, 10, cr),       # no such variant
         (0, 101, 100, 1, 0, 0, out, 10, cr),      # n > N without replacement
         (1, 5, 0, 1, 0, 0, out, 10, cr),          # empty universe with replacement
-        (0, 10, 2**52 + 1, 1, 0, 0, out, 10, cr), # universe too large
+        (0, 10, 2**62 + 1, 1, 0, 0, out, 10, cr), # universe too large
         (0, 10, 100, 1, 46, 0, out, 10, cr),      # depth beyond the maximum
         (0, 10, 100, 1, 3, 8, out, 10, cr),       # index >= 2^depth
         (0, 10, 100, 1, 3, 1, out, 10, None),     # no count/rank buffer
@@ -74,11 +74,11 @@ def test_graph_entry_points_reject_bad_arguments_before_any_device_call():
     ok = ctypes.c_void_p(16)
     odd = ctypes.c_void_p(12)  # not 8-byte aligned
     cnt = ctypes.c_void_p(8)
-    assert L.dcs_sample_edges_gnm(94906267, 1, 1, None, ok, None) == m.DCS_EINVAL  # > 2^52 pairs
+    assert L.dcs_sample_edges_gnm(3037000501, 1, 1, None, ok, None) == m.DCS_EINVAL  # > 2^62 pairs
     assert L.dcs_sample_edges_gnm(10, 46, 1, None, ok, None) == m.DCS_EINVAL       # m > 45 pairs
     assert L.dcs_sample_edges_gnm(10, 5, 1, None, None, None) == m.DCS_EINVAL
     assert L.dcs_sample_edges_gnm(10, 5, 1, None, odd, None) == m.DCS_EINVAL
     assert L.dcs_sample_edges_gnm(10, 0, 1, None, None, None) == m.DCS_OK          # nothing to do
-    assert L.dcs_sample_edges_gnp(94906267, 0.5, 1, None, ok, 10, cnt, None) == m.DCS_EINVAL
+    assert L.dcs_sample_edges_gnp(94906267, 0.5, 1, None, ok, 10, cnt, None) == m.DCS_EINVAL  # > 2^52
     assert L.dcs_sample_edges_gnp(10, 0.5, 1, None, odd, 10, cnt, None) == m.DCS_EINVAL
     assert L.dcs_sample_edges_gnp(10, 0.5, 1, None, None, 10, cnt, None) == m.DCS_EINVAL

@@ -9,7 +9,8 @@ from tests.gpu_util import announce, dcs, first_mismatch
 
 pytestmark = pytest.mark.gpu
 
-MAX_VERTICES = 94906266  # largest n with n(n-1)/2 <= 2^52
+MAX_VERTICES = 94906266  # largest n with n(n-1)/2 <= 2^52 (the G(n, p) bound)
+MAX_VERTICES_GNM = 3037000500  # largest n with n(n-1)/2 <= 2^62 (the G(n, m) bound)
 
 
 def _np_edges(t):
@@ -22,7 +23,9 @@ def _np_edges(t):
     (2, 1, 5),
     (100000, 1 << 20, 6),       # ~2e-4 of all pairs, non-power-of-two universe
     (1 << 16, 1 << 20, 8),      # pairs of 2^16 vertices
-    (MAX_VERTICES, 20000, 7),   # largest universe the library accepts
+    (MAX_VERTICES, 20000, 7),   # 2^52 pairs
+    (1 << 30, 1 << 20, 10),     # 2^30 vertices: about 2^59 pairs
+    (MAX_VERTICES_GNM, 30000, 11),  # largest universe of G(n, m)
     (3000, 0, 9),               # no edges
 ])
 def test_gnm_matches_oracle(ref, n, m, seed):

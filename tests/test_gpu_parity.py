@@ -31,8 +31,11 @@ WOR_CASES = [
     (100000, 2**40 + 3, 12, 512, 16),         # range-forced depth, small n0
     (77777, 300000, 13, 64, 16),              # dense leaves, small n0 (many leaves)
     (50000, 2**44, 14, 4096, 16),             # very sparse
-    (200, 2**52, 15, 4096, 16),               # largest universe
+    (200, 2**52, 15, 4096, 16),               # 2^52: integers still exact in doubles
     (3, 2**52, 16, 2, 16),                    # n0 = 2, depth 50
+    (1 << 22, 2**60, 25, 4096, 16),           # above 2^53: rounded conversions in the splits
+    (300_000, 2**62, 26, 4096, 16),           # largest universe
+    (3, 2**62 - 1, 27, 2, 16),                # n0 = 2, depth 60
     (20000, 640000, 17, 4096, 16),            # density 1/32: sparse, duplicates common
     # ~17 repeated draws per leaf over ~1500 leaves: repeats inside the last
     # sorting window of a leaf, power-of-two and other leaf ranges
@@ -124,6 +127,8 @@ def test_config1_invariants_and_repeatability():
 
 WR_CASES = [
     (1 << 20, 1 << 34, 7, 4096),
+    (1 << 20, 2**61 + 3, 8, 4096),   # above 2^53
+    (5000, 2**62, 9, 64),            # largest universe
     (7, 1, 3, 4096),                 # N = 1: all ones
     (1 << 18, 2, 5, 4096),           # constant leaves cut into pieces
     (100000, 3 * 10**6 + 1, 11, 512),
@@ -254,7 +259,7 @@ def test_invalid_arguments_rejected():
     import torch
     m = dcs()
     out = torch.empty(16, dtype=torch.int64, device="cuda")
-    for args in [(11, 10, 1), (1, 2**52 + 1, 1)]:
+    for args in [(11, 10, 1), (1, 2**62 + 1, 1)]:
         with pytest.raises(m.DcsError):
             m.sample(*args, out=out)
     with pytest.raises(m.DcsError):

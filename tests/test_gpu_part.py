@@ -109,6 +109,8 @@ def test_parts_of_the_8gib_sample(ref):
     (200, 2**52, 45, 2**44 + 12345, 0),  # deepest cut, largest universe
     (200, 2**52, 45, 0, 0),              # its leftmost part holds the leaf above the cut
     (5000, 2**52, 40, 2**39, 1),         # with replacement, deep cut
+    (30000, 2**62, 45, 2**44 + 3, 0),    # largest universe of the tree
+    (30000, 2**61 + 7, 20, 77777, 1),    # with replacement above 2^53
 ])
 def test_part_edge_cases(ref, n, N, depth, index, variant):
     import torch

@@ -86,9 +86,9 @@ def test_lnfact_diff_bitexact(ref):
     announce("lnfact_diff")
     rng = np.random.default_rng(5)
     a = np.concatenate([rng.integers(0, 2000, 200000), rng.integers(0, 2**52, 200000),
-                        rng.integers(60, 70, 1000)]).astype(np.uint64)
+                        rng.integers(2**52, 2**62, 100000), rng.integers(60, 70, 1000)]).astype(np.uint64)
     d = rng.integers(-2**20, 2**20, a.size)
-    b = np.clip(a.astype(np.int64) + d, 0, 2**52).astype(np.uint64)
+    b = np.clip(a.astype(np.int64) + d, 0, 2**62).astype(np.uint64)
     b[:1000] = rng.integers(0, 1100, 1000).astype(np.uint64)
     y = _run(m, 5, a, b, torch.float64, a.size)
     assert np.array_equal(y.view(np.uint64), ref.lnfact_diff_batch(a, b).view(np.uint64))
@@ -96,7 +96,9 @@ def test_lnfact_diff_bitexact(ref):
 
 HYP = [(5, 7, 20), (16, 16, 40), (17, 40, 90), (300, 200, 1000), (700, 400, 1000),
        (900, 700, 1000), (1 << 30, 1 << 47, 1 << 48), (4095, 2**31, 2**32),
-       (3_000_000, 2**41 - 1, 2**42 - 1), (1 << 20, 1 << 31, 1 << 32), (2, 2**51, 2**52)]
+       (3_000_000, 2**41 - 1, 2**42 - 1), (1 << 20, 1 << 31, 1 << 32), (2, 2**51, 2**52),
+       (1000, 2**59, 2**60), (1 << 24, 2**59 + 12345, 2**60 + 99), (12, 2**61, 2**62),
+       (50_000, 3 * 2**59, 2**62 - 1)]
 
 
 @pytest.mark.parametrize("n,M,N", HYP)
@@ -110,7 +112,8 @@ def test_hypergeometric_bitexact(ref, n, M, N):
 
 
 BIN = [(5, 3, 7), (16, 5, 10), (17, 1, 2), (100, 500, 1000), (1000, 3, 7),
-       (1 << 28, 1 << 39, 1 << 40), (10**7, 2**32, 2**33 + 1)]
+       (1 << 28, 1 << 39, 1 << 40), (10**7, 2**32, 2**33 + 1), (30_000, 2**60, 2**61 + 3),
+       (9, 2**61, 2**62 - 1)]
 
 
 @pytest.mark.parametrize("n,l,Nv", BIN)

@@ -94,13 +94,17 @@ def test_segments_large(ref, K, n, seed):
 
 
 def test_segments_rejects_bad_arguments():
+    """Refused before anything is enqueued; the output buffer is real, so
+    that a check that let a call through could not write elsewhere."""
     import ctypes
+    import torch
     m = dcs()
-    L = (ctypes.c_uint64 * 2)(1 << 52, 1)
-    rc = m.lib().dcs_sample_segments(1, L, 2, 1, None, ctypes.c_void_p(8), None, None)
-    assert rc == m.DCS_EINVAL
+    out = torch.zeros(16, dtype=torch.int64, device="cuda")
+    p = ctypes.c_void_p(out.data_ptr())
+    L = (ctypes.c_uint64 * 2)(1 << 62, 1)  # sum above the largest universe
+    assert m.lib().dcs_sample_segments(1, L, 2, 1, None, p, None, None) == m.DCS_EINVAL
     L1 = (ctypes.c_uint64 * 1)(10)
-    assert m.lib().dcs_sample_segments(11, L1, 1, 1, None, ctypes.c_void_p(8), None,
-                                       None) == m.DCS_EINVAL
-    assert m.lib().dcs_sample_segments(1, L1, 0, 1, None, ctypes.c_void_p(8), None,
-                                       None) == m.DCS_EINVAL
+    assert m.lib().dcs_sample_segments(11, L1, 1, 1, None, p, None, None) == m.DCS_EINVAL
+    assert m.lib().dcs_sample_segments(1, L1, 0, 1, None, p, None, None) == m.DCS_EINVAL
+    m.synchronize()
+    assert int(out.abs().sum().item()) == 0

@@ -50,11 +50,17 @@ def test_wholerange_benchmarked_size(ref):
 
 
 def test_wholerange_refused():
+    """Refused before anything is enqueued (the output buffer is real, so
+    that a check that let a call through could not write elsewhere)."""
     import ctypes
+    import torch
     m = dcs()
     L = m.lib()
-    p = ctypes.c_void_p(8)
+    out = torch.zeros(16, dtype=torch.int64, device="cuda")
+    p = ctypes.c_void_p(out.data_ptr())
     assert L.dcs_sample_wholerange(1, 1 << 20, 1, None, p, None) == m.DCS_ENOTSUP
     assert L.dcs_sample_wholerange(10, (1 << 32) + 1, 1, None, p, None) == m.DCS_EINVAL
     assert L.dcs_sample_wholerange(5, 4, 1, None, p, None) == m.DCS_EINVAL
     assert L.dcs_sample_wholerange(0, 100, 1, None, None, None) == m.DCS_OK
+    m.synchronize()
+    assert int(out.abs().sum().item()) == 0
