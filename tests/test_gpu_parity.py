@@ -129,6 +129,8 @@ WR_CASES = [
     (1 << 20, 1 << 34, 7, 4096),
     (1 << 20, 2**61 + 3, 8, 4096),   # above 2^53
     (5000, 2**62, 9, 64),            # largest universe
+    (3000, 2**31 + 1, 10, 4096),     # half of all words void: values drawn beyond the first 4096 words
+    (1 << 20, 3 * 2**40 + 5, 11, 4096),  # leaves over ranges just above 2^31 (up to half void)
     (7, 1, 3, 4096),                 # N = 1: all ones
     (1 << 18, 2, 5, 4096),           # constant leaves cut into pieces
     (100000, 3 * 10**6 + 1, 11, 512),
