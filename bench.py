@@ -28,15 +28,31 @@ N0 = 4096
 BYTES_PER_SAMPLE = 8
 
 
-# HBM bytes per k_leaf_pow2 launch on the workload above, from rocprofv3 FETCH_SIZE
-# and WRITE_SIZE passes scaled by the same counters on a plain copy kernel (the
-# profile summaries under profiles/ give the commands and raw figures).  They
-# describe the kernel as built from the sources with this digest and are
-# reported only while the sources still match it.
-LEAF_TRAFFIC = {
-    "sources_sha256": "0bddef5ff3ff7e2165a969cc9444b26c7ed29f8a32ee293642b362ede86bdb7e",
-    "fetch_bytes": 70_665_953,      # 34504.9 KiB FETCH_SIZE x 2.0
-    "write_bytes": 8_880_839_823,   # 8672695.1 KiB WRITE_SIZE x 1.0
+# HBM bytes per launch of each configuration's dominant kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes scaled by the same counters on a 1 GiB copy
+# (x2.0 and x1.0; the profile summaries under profiles/ give the commands and
+# raw figures), next to the kernel's algorithmic bytes.  They describe the
+# kernels as built from the sources with this digest and are reported only
+# while the sources still match it.
+TRAFFIC_SOURCES_SHA256 = "397ba0315b12f654e0d3909d837fce12cdd8bd6970eedc60d1c28f5215c94f48"
+LEAF_TRAFFIC = {  # k_leaf_pow2, n = 2^30 of N = 2^48
+    "fetch_bytes": 70_757_320,      # 34551.1 KiB FETCH_SIZE x 2.0
+    "write_bytes": 8_880_777_984,   # 8672634.8 KiB WRITE_SIZE x 1.0
+}
+CONFIG_TRAFFIC = {
+    "c1_wor_2^20_of_2^32": {"kernel": "k_leaf_pow2", "fetch_bytes": 612_415,
+                            "write_bytes": 12_135_765, "algorithmic_bytes": 8_388_608},
+    "c2b_wor_dense_2^29_of_2^30": {"kernel": "k_leaf_dense", "fetch_bytes": 38_055_594,
+                                   "write_bytes": 4_826_535_968,
+                                   "algorithmic_bytes": 4_294_967_296},
+    "c3a_bernoulli_p0.01_of_2^36": {"kernel": "k_bern_wave", "fetch_bytes": 229_017_531,
+                                    "write_bytes": 5_914_315_242,
+                                    "algorithmic_bytes": 5_497_618_384},
+    "c3b_wr_2^28_of_2^40": {"kernel": "k_leaf_pow2", "fetch_bytes": 23_159_272,
+                            "write_bytes": 2_229_162_325, "algorithmic_bytes": 2_147_483_648},
+    "c2b_wholerange_B_2^29_of_2^30": {"kernel": "k_wb_write", "fetch_bytes": 171_967_056,
+                                      "write_bytes": 4_669_429_706,
+                                      "algorithmic_bytes": 4_362_099_332},
 }
 KERNEL_SOURCES = ("dcs_kernels.hip", "dcs_kernels.hpp", "dcs_device.hpp")
 
@@ -51,10 +67,20 @@ def kernel_sources_digest() -> str:
 
 
 def recorded_traffic():
-    t = LEAF_TRAFFIC
-    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_digest():
+    if TRAFFIC_SOURCES_SHA256 != kernel_sources_digest():
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    return LEAF_TRAFFIC["fetch_bytes"] + LEAF_TRAFFIC["write_bytes"]
+
+
+def config_traffic(name: str):
+    """Recorded HBM bytes of a configuration's dominant kernel, or None when
+    none were taken or the kernel sources have changed since."""
+    t = CONFIG_TRAFFIC.get(name)
+    if t is None or TRAFFIC_SOURCES_SHA256 != kernel_sources_digest():
+        return None
+    return dict(t, traffic_bytes=t["fetch_bytes"] + t["write_bytes"],
+                traffic_over_algorithmic=(t["fetch_bytes"] + t["write_bytes"])
+                / t["algorithmic_bytes"])
 
 
 def host_description() -> dict:
@@ -117,7 +143,7 @@ def cpu_baseline(gpu_out, budget_s: float = 12.0, max_threads: int = 16):
     }
 
 
-def bench_batched(dcs, reps: int = 3):
+def bench_batched(dcs, reps: int = 3, plain: bool = True):
     """4096 uneven instances (n log-uniform in [2^8, 2^22], density in
     [1e-6, 0.5], seeds 0..4095): one hipGraph-replayed batch vs one plain
     dcs_sample call per instance on one stream (synchronized once)."""
@@ -144,6 +170,12 @@ def bench_batched(dcs, reps: int = 3):
             b.run(out, use_graph=True, stream=stream)
     dcs.synchronize(stream)
     batched_s = (time.perf_counter() - t0) / reps
+    if not plain:  # the batch alone (e.g. under a counter profiler)
+        b.close()
+        del out
+        torch.cuda.empty_cache()
+        return {"samples": total, "batched_ms": batched_s * 1e3,
+                "batched_samples_per_s": total / batched_s}
     # plain: one call per instance into the same buffer
     with torch.cuda.stream(stream):
         for s_, x in zip(specs, insts):
@@ -242,6 +274,7 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
             "kernels_ms": avgs,
             "dominant_kernel_write_GBs": 8 * samples / (k_avg * 1e-3) / 1e9 if k_avg > 0 else None,
             "tree_ms": (t_ms / t_n) if t_n else None,
+            "traffic": config_traffic(name),
         }
         del out
         torch.cuda.empty_cache()
@@ -450,6 +483,8 @@ def main() -> int:
     ap.add_argument("--no-parts", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-segments", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="batched: time the batch without the per-instance plain calls")
     ap.add_argument("--only", default=None,
                     help="comma list of other configurations (c1, c2b, c3a, c3b, batched, "
                          "parts, graph, segments, serving) to run alone, e.g. under a profiler; "
@@ -464,14 +499,27 @@ def main() -> int:
     import paper_1610_05141_amd as dcs
 
     torch.cuda.set_device(0)
+
+    def copy_calibration():
+        # 1 GiB fill (writes 2^30 B) then 1 GiB copy (reads and writes 2^30 B)
+        a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+        b = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+        b.fill_(1)
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+
     if args.only:
+        if args.copy_calibration:
+            copy_calibration()
         names = args.only.split(",")
         res = {}
         other = [x for x in names if x not in ("batched", "serving", "parts", "graph", "segments")]
         if other:
             res.update(bench_other_configs(dcs, reps=args.steps, only=other))
         if "batched" in names:
-            res["batched"] = bench_batched(dcs)
+            res["batched"] = bench_batched(dcs, plain=not args.batched_only)
         if "parts" in names:
             res["parts"] = bench_parts(dcs)
         if "graph" in names:
@@ -490,13 +538,7 @@ def main() -> int:
     dcs.synchronize(stream)
 
     if args.copy_calibration:
-        # 1 GiB fill (writes 2^30 B) then 1 GiB copy (reads and writes 2^30 B)
-        a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
-        b = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
-        b.fill_(1)
-        a.copy_(b)
-        torch.cuda.synchronize()
-        del a, b
+        copy_calibration()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     # inside the timed steps only the roofline kernel carries HIP events
