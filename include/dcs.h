@@ -134,6 +134,16 @@ int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed,
  * error of the call (it cannot be known when the call returns): compare
  * *count_dev with capacity after synchronizing; re-running with a larger
  * buffer gives the identical sample.
+ * Concurrency: the chunks' output offsets come from a decoupled look-back in
+ * which a chunk waits for its predecessors' counts.  Chunks are handed out
+ * by seven counters (chunk j by counter j mod 7, in order within each), so
+ * progress needs a running work-group of every class; the launch sizes its
+ * grid so that every class has one when the kernel has the GPU to itself.
+ * Do not run a Bernoulli call (or G(n, p)) concurrently with other long
+ * kernels on another stream: if the other kernel keeps a class from running,
+ * waves poll up to 2^26 times (seconds), then the call latches an error
+ * (DCS_EDEVICE at dcs_synchronize) and the sample is lost.  Calls on one
+ * stream, or concurrent with short kernels only, are unaffected.
  */
 int32_t dcs_sample_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t* out_dev,
                              uint64_t capacity, uint64_t* count_dev, void* stream);
@@ -383,6 +393,38 @@ int32_t dcs_tune_set(int32_t variant, uint32_t log2_n, int32_t cut_bias, uint32_
 int32_t dcs_tune_get(int32_t variant, uint32_t log2_n, int32_t* cut_bias,
                      uint32_t* leaf_wgs_per_cu);
 int32_t dcs_tune_reset(void);
+
+/*
+ * Leaf-job capacity (plan of every tree call: samples, parts, batches,
+ * served requests, segments, G(n, m)).  The leaf jobs of the recursion tree
+ * are bounded for every outcome of its random splits (at most n, and at
+ * most 2I + 1 for I internal nodes, of which at most n/n0 per level hold n0
+ * or more values); a call is planned with that bound when its job records
+ * take at most 48 MiB or 4x the expected-case capacity (about 1.5 n/n0
+ * jobs, planned with 4 n/n0 + slack), and overflow is then impossible.
+ * Otherwise it is planned with the expected-case capacity and a second
+ * round on the device: a tree thread whose leaf finds the job array full is
+ * marked, and after the first leaf pass the marked threads run again into
+ * the emptied array (their leaves' values go to fixed places, so a leaf
+ * sampled in both rounds is written twice with the same values).  Only if
+ * the second round runs out of slots too does dcs_synchronize report
+ * DCS_EDEVICE (the sample is incomplete); later plans in the process then
+ * multiply the expected-case capacity by 4 (up to 64x), so that calling
+ * again gives the sample.
+ * dcs_debug_leaf_capacity -- test hook: plan every later tree call with
+ * `capacity` job slots per instance (at least one more than its top-level
+ * paths) and the second round; 0 restores normal planning.  *boost (if not
+ * NULL) receives the current multiplier; reset_boost != 0 then sets it back
+ * to 1.  DCS_EINVAL if capacity >= 2^31.
+ */
+int32_t dcs_debug_leaf_capacity(uint64_t capacity, int32_t reset_boost, uint32_t* boost);
+/* dcs_debug_plan -- the plan of a tree call (host only, no device work):
+ * info[0] cut depth, [1] tree threads, [2] DFS stack entries per thread,
+ * [3] leaf-job capacity, [4] the proven bound on leaf jobs, [5] 1 if the
+ * second round is planned.  DCS_EINVAL on the argument errors of
+ * dcs_sample_ex / dcs_sample_replacement_ex, a bad variant or info NULL. */
+int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params* params,
+                       uint64_t* info);
 
 /* Human-readable name of a status code (static storage). */
 const char* dcs_status_string(int32_t status);

@@ -38,7 +38,8 @@ EXPORTED_SYMBOLS = (
     "dcs_profile_read", "dcs_profile_kinds", "dcs_debug_primitive", "dcs_server_create", "dcs_server_submit",
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
-    "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset",
+    "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset", "dcs_debug_leaf_capacity",
+    "dcs_debug_plan",
 )
 
 
@@ -129,6 +130,8 @@ def lib() -> ctypes.CDLL:
             "dcs_tune_set": (i32, [i32, u32, i32, u32]),
             "dcs_tune_get": (i32, [i32, u32, ctypes.POINTER(i32), ctypes.POINTER(u32)]),
             "dcs_tune_reset": (i32, []),
+            "dcs_debug_leaf_capacity": (i32, [u64, i32, ctypes.POINTER(u32)]),
+            "dcs_debug_plan": (i32, [i32, u64, u64, pp, ctypes.POINTER(u64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -390,6 +393,28 @@ def tune_get(variant: int, log2_n: int):
 
 def tune_reset() -> None:
     _check(lib().dcs_tune_reset(), "dcs_tune_reset")
+
+
+def debug_plan(variant: int, n: int, N: int, n0: int = 0, dense_ratio: int = 0) -> dict:
+    """The plan of a tree call (host only): cut depth, tree threads, DFS
+    stack entries per thread, leaf-job capacity, proven bound on leaf jobs,
+    and whether the second round is planned."""
+    info = (ctypes.c_uint64 * 6)()
+    _check(lib().dcs_debug_plan(variant, n, N, _params(n0, dense_ratio), info), "dcs_debug_plan")
+    return {"cut": int(info[0]), "threads": int(info[1]), "stack_depth": int(info[2]),
+            "leaf_cap": int(info[3]), "leaf_bound": int(info[4]),
+            "second_round": bool(info[5])}
+
+
+def debug_leaf_capacity(capacity: int, reset_boost: bool = False) -> int:
+    """Test hook: plan later tree calls with `capacity` leaf-job slots per
+    instance and the device's second round (0: normal planning).  Returns the
+    multiplier of the expected-case capacity in effect (raised after a call
+    ran out of slots in both rounds), then resets it to 1 if asked."""
+    b = ctypes.c_uint32(0)
+    _check(lib().dcs_debug_leaf_capacity(int(capacity), 1 if reset_boost else 0,
+                                         ctypes.byref(b)), "dcs_debug_leaf_capacity")
+    return int(b.value)
 
 
 def profile_kinds(kinds=None):

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -64,6 +65,69 @@ int32_t read_params(const dcs_params* p, Params* out) {
 }
 
 
+uint64_t sat_add(uint64_t a, uint64_t b) { return a + b < a ? ~0ull : a + b; }
+
+// Leaf jobs of the canonical tree, bounded for every outcome of its random
+// splits.  Every job is a non-empty child of an internal node, the root, or
+// an extra piece of a constant leaf (at most n / kFillPiece of those), so
+// there are at most 2 I + 1 + n / kFillPiece, and at most n (each holds a
+// value).  I counts internal nodes level by level: at depth d at most 2^d
+// nodes, and at most n, are non-empty; where no range exceeds 2^32 a node
+// splits only if it holds n0 or more values, and at most n / n0 such nodes
+// are disjoint.  Without replacement that needs N_v >= n_v >= n0, with
+// replacement N_v >= 2, which ends the levels.
+uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
+  if (n == 0) return 0;
+  const uint64_t need = variant == 0 ? n0 : 2;
+  uint64_t internal = 0;
+  for (uint32_t d = 0; d < 64; ++d) {
+    const uint64_t widest = ceil_div_pow2(N, d);
+    const bool forced = widest > kLeafRange;
+    if (!forced && widest < need) break;
+    const uint64_t nodes = d < 63 ? (1ull << d) : ~0ull;
+    internal = sat_add(internal, std::min(nodes, forced ? n : n / n0));
+  }
+  uint64_t jobs = sat_add(sat_add(internal, internal), 1);
+  if (variant == 1) jobs = sat_add(jobs, n / dcs::kFillPiece);
+  return std::min(jobs, n);
+}
+
+// A capacity below the proven bound is used once the bound needs more than
+// this many jobs (48 MiB of job records) and more than 4x the expected-case
+// capacity.
+constexpr uint64_t kProvenJobs = 1ull << 20;
+// Test hook (dcs_debug_leaf_capacity): a fixed capacity with the second
+// round, 0 = off.  Multiplier of the expected-case capacity, raised after a
+// call latched a capacity error.
+std::atomic<uint64_t> g_debug_leaf_cap{0};
+std::atomic<uint32_t> g_cap_boost{1};
+
+void leaf_capacity_exceeded() {
+  uint32_t b = g_cap_boost.load();
+  while (b < 64 && !g_cap_boost.compare_exchange_weak(b, b * 4)) {
+  }
+}
+
+// Capacity from the expected-case estimate and the proven bound (see
+// make_plan); *second: the launch needs the second round.
+uint64_t choose_capacity(uint64_t expected, uint64_t proven, uint64_t top_threads, bool* second) {
+  const uint64_t debug_cap = g_debug_leaf_cap.load();
+  const uint64_t boosted = expected * g_cap_boost.load();
+  uint64_t cap;
+  *second = false;
+  if (debug_cap != 0) {
+    cap = debug_cap;
+    *second = true;
+  } else if (proven <= std::max(kProvenJobs, 4 * boosted)) {
+    cap = proven;
+  } else {
+    cap = boosted;
+    *second = true;
+  }
+  // the top kernel's leaves (at most one per top path) always fit
+  return std::max<uint64_t>(cap, top_threads + 1);
+}
+
 // variant 0: without replacement, 1: with replacement.
 Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias) {
   Plan pl;
@@ -86,24 +150,32 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
   pl.top_cut = cut > 6 ? cut - 6 : 0;
   pl.top_threads = 1ull << pl.top_cut;
   // Deepest possible internal node: its range must reach n0 (without
-  // replacement: n_v <= N_v) or 2 (with replacement), or exceed 2^32.
+  // replacement: n_v <= N_v) or 2 (with replacement), or exceed 2^32.  The
+  // depth-first walk below the cut holds at most one pending right child
+  // per level, so this stack bound is never exceeded.
   const uint64_t need_range = variant == 0 ? std::min<uint64_t>(n0, kLeafRange + 1) : 2;
   uint32_t d_int = 0;
   while (d_int < 63 && ceil_div_pow2(N, d_int + 1) >= need_range) ++d_int;
   pl.stack_depth = (d_int + 2 > cut) ? d_int + 2 - cut : 2;
-  // Leaf capacity: the tree has about 1.5 n/n0 leaves (at most n/n0 internal
-  // nodes per level, halving sizes); range-forced levels add at most
-  // min(n, 2^(forced+1)) small leaves; constant pieces of N_v = 1 leaves.
+  // Leaf capacity.  Expected case: the tree has about 1.5 n/n0 leaves (at
+  // most n/n0 internal nodes per level, halving sizes); range-forced levels
+  // add at most min(n, 2^(forced+1)) small leaves; constant pieces of
+  // N_v = 1 leaves.  The proven bound is used where it is affordable;
+  // otherwise the expected-case capacity with the second round (tree
+  // threads whose leaves found the job array full run again into the
+  // emptied array), which only a deviation far beyond the expected leaf
+  // count would exhaust too.
   uint64_t cap = 4 * ((n + n0 - 1) / n0) + 64;
   cap += std::min<uint64_t>(n, forced >= 62 ? n : (2ull << forced));
   if (variant == 1) cap += n / dcs::kFillPiece + std::min<uint64_t>(N, 4 * (n / n0) + 4) + 2;
-  pl.leaf_cap = cap;
+  pl.leaf_cap = choose_capacity(cap, leaf_bound(n, N, n0, variant), pl.top_threads,
+                                &pl.second_round);
   return pl;
 }
 
 
 TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth,
-                       uint64_t top_threads) {
+                       uint64_t top_threads, bool second_round) {
   TreeLayout L;
   size_t o = 0;
   L.ctl = o;
@@ -116,6 +188,9 @@ TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uin
   o = align_up(o + sizeof(Node) * threads * stack_depth);
   L.frontier = o;
   o = align_up(o + sizeof(Node) * std::max<uint64_t>(top_threads, 1));
+  L.redo = o;
+  L.redo_words = second_round ? (threads + 31) / 32 : 0;
+  o = align_up(o + sizeof(uint32_t) * L.redo_words);
   L.total = o;
   return L;
 }
@@ -357,9 +432,10 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   Leaf* leaves = reinterpret_cast<Leaf*>(base + L.leaves);
   Node* stacks = reinterpret_cast<Node*>(base + L.stacks);
   Node* frontier = reinterpret_cast<Node*>(base + L.frontier);
+  uint32_t* redo = L.redo_words ? reinterpret_cast<uint32_t*>(base + L.redo) : nullptr;
   Timing t0{}, t1{}, t2{};
   timing_begin(0, s, &t0);
-  hipError_t e = dcs::launch_reset(ctl, single, inst, err, s);
+  hipError_t e = dcs::launch_reset(ctl, single, inst, err, redo, L.redo_words, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   timing_begin(1, s, &t1);
@@ -367,7 +443,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
                            s);
   if (e == hipSuccess)
     e = dcs::launch_tree(inst, n_inst, threads, frontier, leaves, leaf_cap, stacks, stack_depth,
-                         ctl, s);
+                         ctl, redo, 0, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
   uint64_t want = static_cast<uint64_t>(c->cus) * std::max<uint32_t>(1, leaf_wgs_per_cu);
@@ -401,6 +477,14 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
     e = dcs::launch_leaf_small(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(waves), s);
     timing_end(s, &t12);
   }
+  // Second round: the tree threads marked in `redo` run again into the
+  // emptied job array, and one work-group pass samples their leaves (both
+  // return at once when nothing was marked).
+  if (e == hipSuccess && redo != nullptr)
+    e = dcs::launch_tree(inst, n_inst, threads, frontier, leaves, leaf_cap, stacks, stack_depth,
+                         ctl, redo, 1, s);
+  if (e == hipSuccess && redo != nullptr)
+    e = dcs::launch_leaf_round2(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
   return DCS_OK;
@@ -425,7 +509,8 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
   const Plan pl = make_plan(n, N, P.n0, variant, cut_bias_for(variant, n));
-  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
+  const TreeLayout L =
+      tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads, pl.second_round);
   void* ws = workspace;
   if (noalloc) {
     if (L.total > DCS_NOALLOC_SCRATCH_BYTES) return DCS_ENOMEM;
@@ -565,7 +650,8 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
   np = std::max<uint64_t>(np, 1);
   const Plan pl = make_plan(np, std::max<uint64_t>(range, 1), P.n0, static_cast<uint32_t>(variant),
                             cut_bias_for(static_cast<uint32_t>(variant), np));
-  const TreeLayout L = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads);
+  const TreeLayout L =
+      tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads, pl.second_round);
   void* ws = nullptr;
   rc = own_workspace(c, L.total, &ws);
   if (rc) return rc;
@@ -614,7 +700,7 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
   // leaves of all segments together (at most 4 n/n0 + 5 per non-empty
   // segment, plus the leaves of levels forced by ranges above 2^32).
   std::vector<Instance> tab(K);
-  uint64_t tb = 0, tt = 0, forced_leaves = 0, nonempty = 0;
+  uint64_t tb = 0, tt = 0, forced_leaves = 0, nonempty = 0, proven = 0;
   uint32_t stack_depth = 1;
   uint64_t base = 0;
   for (uint64_t i = 0; i < K; ++i) {
@@ -641,10 +727,14 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
     while (ceil_div_pow2(lengths[i], forced) > kLeafRange) ++forced;
     if (forced > 0) forced_leaves += std::min<uint64_t>(n, 2ull << forced);
     ++nonempty;
+    // a segment holds at most min(n, L_i) values
+    proven = sat_add(proven, leaf_bound(std::min(n, lengths[i]), lengths[i], P.n0, 0));
   }
-  const uint64_t leaf_cap =
-      4 * ((n + P.n0 - 1) / P.n0) + 64 + 5 * nonempty + std::min<uint64_t>(n, forced_leaves);
-  const TreeLayout L = tree_layout(static_cast<uint32_t>(K), leaf_cap, tb, stack_depth, tt);
+  bool second = false;
+  const uint64_t leaf_cap = choose_capacity(
+      4 * ((n + P.n0 - 1) / P.n0) + 64 + 5 * nonempty + std::min<uint64_t>(n, forced_leaves),
+      std::min(proven, n), tt, &second);
+  const TreeLayout L = tree_layout(static_cast<uint32_t>(K), leaf_cap, tb, stack_depth, tt, second);
   void* ws = nullptr;
   rc = own_workspace(c, L.total, &ws);
   if (rc) return rc;
@@ -806,7 +896,8 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
     std::lock_guard<std::mutex> lk(g_mu);
     const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant),
                               cut_bias_for(static_cast<uint32_t>(variant), n));
-    *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads).total;
+    *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads,
+                         pl.second_round).total;
     return DCS_OK;
   }
   if (variant == 2) {
@@ -830,6 +921,7 @@ struct dcs_batch {
   std::vector<Instance> host;
   uint64_t threads = 0, top_threads = 0, leaf_cap = 0, total_out = 0;
   uint32_t stack_depth = 1;
+  bool second_round = false;
   TreeLayout layout;
   void* ws = nullptr;
   int device = 0;
@@ -875,13 +967,15 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
     tb += pl.threads;
     tt += pl.threads ? pl.top_threads : 0;
     b->leaf_cap += pl.leaf_cap;
+    b->second_round = b->second_round || pl.second_round;
     b->stack_depth = std::max(b->stack_depth, pl.stack_depth);
     b->total_out += d.n;
     b->host.push_back(I);
   }
   b->threads = tb;
   b->top_threads = tt;
-  b->layout = tree_layout(count, b->leaf_cap, b->threads, b->stack_depth, b->top_threads);
+  b->layout = tree_layout(count, b->leaf_cap, b->threads, b->stack_depth, b->top_threads,
+                          b->second_round);
   if (hipGetDevice(&b->device) != hipSuccess || hipMalloc(&b->ws, b->layout.total) != hipSuccess) {
     delete b;
     return DCS_ENOMEM;
@@ -971,6 +1065,8 @@ int32_t dcs_synchronize(void* stream) {
   if (any != 0 && (hipMemsetAsync(word, 0, sizeof(unsigned int), s) != hipSuccess ||
                    hipStreamSynchronize(s) != hipSuccess))
     return DCS_EHIP;
+  // both rounds of a call ran out of job slots: plan larger capacities
+  if (any & dcs::kErrLeafCapacity) leaf_capacity_exceeded();
   if (g_profile) {
     for (Timing& t : g_timings) {
       float ms = 0;
@@ -1021,6 +1117,33 @@ int32_t dcs_tune_reset(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& row : g_tune)
     for (auto& t : row) t = Tune{};
+  return DCS_OK;
+}
+
+int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params* params,
+                       uint64_t* info) {
+  Params P;
+  if (info == nullptr || (variant != 0 && variant != 1) || read_params(params, &P) != DCS_OK ||
+      N > DCS_MAX_UNIVERSE || (variant == 0 && n > N) || (variant == 1 && N == 0 && n > 0))
+    return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const uint32_t v = static_cast<uint32_t>(variant);
+  const Plan pl = make_plan(n, N, P.n0, v, cut_bias_for(v, n));
+  info[0] = pl.cut;
+  info[1] = pl.threads;
+  info[2] = pl.stack_depth;
+  info[3] = pl.leaf_cap;
+  info[4] = leaf_bound(n, N, P.n0, v);
+  info[5] = pl.second_round ? 1 : 0;
+  return DCS_OK;
+}
+
+int32_t dcs_debug_leaf_capacity(uint64_t capacity, int32_t reset_boost, uint32_t* boost) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (capacity >= dcs::kMaxLeafJobs) return DCS_EINVAL;
+  g_debug_leaf_cap.store(capacity);
+  if (boost != nullptr) *boost = g_cap_boost.load();
+  if (reset_boost) g_cap_boost.store(1);
   return DCS_OK;
 }
 

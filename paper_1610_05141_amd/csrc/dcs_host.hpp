@@ -31,15 +31,25 @@ struct Plan {
   uint64_t top_threads = 0;  // 2^top_cut (0 for an empty instance)
   uint32_t stack_depth = 1;
   uint64_t leaf_cap = 0;
+  // leaf_cap below the proven bound on the leaf jobs: the launch adds the
+  // second round for tree threads whose leaves did not all fit
+  bool second_round = false;
 };
 Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias);
+// Leaf jobs of the tree of (n, N, n0, variant) for every outcome of its
+// random splits.
+uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant);
+// After a call latched a capacity error: later plans take larger capacities.
+void leaf_capacity_exceeded();
 
-// Workspace layout of a tree launch (byte offsets).
+// Workspace layout of a tree launch (byte offsets).  redo_words > 0: the
+// second round's bitmap over tree threads (redo_words 32-bit words).
 struct TreeLayout {
-  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, frontier = 0, total = 0;
+  size_t ctl = 0, inst = 0, leaves = 0, stacks = 0, frontier = 0, redo = 0, total = 0;
+  uint64_t redo_words = 0;
 };
 TreeLayout tree_layout(uint32_t n_inst, uint64_t leaf_cap, uint64_t threads, uint32_t stack_depth,
-                       uint64_t top_threads);
+                       uint64_t top_threads, bool second_round);
 
 struct DeviceCtx {
   bool init = false;

@@ -1296,15 +1296,23 @@ __device__ void leaf_fill(const Leaf& L, uint64_t* out) {
   for (uint32_t i = threadIdx.x; i < L.nv; i += B) store_out(o + i, L.lo + 1);
 }
 
+// Jobs handed over in a round (front list count in the low 32 bits, back
+// list count in the high 32 bits): those granted slots.
+__device__ __forceinline__ uint64_t job_counts(const Control* ctl, int round) {
+  const unsigned long long g = round ? ctl->granted2 : ctl->granted;
+  return g != ~0ull ? g : (round ? ctl->leaf_counts2 : ctl->leaf_counts);
+}
+
 // Persistent leaf loop: job i of the class's list goes to work-group
 // i mod G, whose job records are read kCacheLeaves at a time into LDS.
 // kPow2: the front list (sparse and with-replacement leaves over power-of-two
 // ranges) with only that leaf body compiled in, so that the hot path keeps
 // its values in registers; otherwise the back list with every other leaf
-// body.
+// body.  round2: the second round's jobs (back list only, every kind, none
+// left to the one-wave kernels).
 template <int B, bool kPow2>
 __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
-                                          uint64_t* out, Control* ctl) {
+                                          uint64_t* out, Control* ctl, int round2 = 0) {
   __shared__ uint32_t smem[kSmemWords];
   LeafSmem sm;
   sm.keys = smem;
@@ -1314,11 +1322,11 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
   sm.mask = sm.buck + kKeys;
   uint32_t* cache = smem + kRegionA + kRegionB;
   sm.scr = cache + kCacheWords;
-  const uint64_t counts = uniform64(ctl->leaf_counts);
+  const uint64_t counts = uniform64(job_counts(ctl, round2));
   const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
   if (front + back > leaf_cap) {
-    // the lists overlap (or one overflowed): the tree kernel flagged or
-    // would have flagged capacity; report it and sample nothing
+    // cannot happen (granted slots sum to at most the capacity): report it
+    // and sample nothing
     if (!kPow2 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(ctl->err, kErrLeafCapacity);
     return;
   }
@@ -1359,7 +1367,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
             c.Nv = static_cast<uint64_t>(r[4]) | (static_cast<uint64_t>(r[5]) << 32);
             c.nv = r[10];
             c.flags = r[11];
-            run = !dense_by_wave(c) && !small_by_wave(c);
+            run = round2 || (!dense_by_wave(c) && !small_by_wave(c));
           }
           const unsigned long long m = __ballot(run);
           if (tid == 0) sm.scr[kScrKeep] = static_cast<uint32_t>(m);
@@ -1420,8 +1428,8 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
 
 template <int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_mixed(
-    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl) {
-  leaf_loop<B, false>(leaves, leaf_cap, out, ctl);
+    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl, int round2) {
+  leaf_loop<B, false>(leaves, leaf_cap, out, ctl, round2);
 }
 
 // Dense leaves of the back list, one wave (and work-group) per leaf: back job
@@ -1431,7 +1439,7 @@ __global__ __launch_bounds__(64) void k_leaf_dense(const Leaf* __restrict__ leav
   __shared__ __align__(16) uint16_t list[kWaveList];
   __shared__ uint32_t mask[kWaveMaskWords];
   __shared__ uint32_t bases[kWaveBases];
-  const uint64_t counts = uniform64(ctl->leaf_counts);
+  const uint64_t counts = uniform64(job_counts(ctl, 0));
   const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
   if (front + back > leaf_cap) return;  // reported by k_leaf_mixed
   for (uint64_t i = blockIdx.x; i < back; i += gridDim.x) {
@@ -1455,7 +1463,7 @@ __global__ __launch_bounds__(64) void k_leaf_small(const Leaf* __restrict__ leav
                                                    uint64_t leaf_cap, uint64_t* out, Control* ctl) {
   __shared__ __align__(16) uint32_t keys[kSmallKeys];
   __shared__ __align__(16) uint32_t cnt[kSmallCnt];
-  const uint64_t counts = uniform64(ctl->leaf_counts);
+  const uint64_t counts = uniform64(job_counts(ctl, 0));
   const uint64_t front = counts & 0xFFFFFFFFull, back = counts >> 32;
   if (front + back > leaf_cap) return;  // reported by k_leaf_mixed
   for (uint64_t i = blockIdx.x; i < back; i += gridDim.x) {
@@ -1488,8 +1496,11 @@ __device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I)
                         : hypergeometric<kWave>(v.nv, l, v.Nv, I.seed, v.id);
 }
 
-__device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* leaves, uint64_t cap,
-                                     Control* ctl) {
+// Hand leaf v over as a job (round 0: front or back list by kind; round 1:
+// back list).  The job's slots are granted iff the slots asked for so far,
+// these included, fit the capacity; returns whether they were.
+__device__ __forceinline__ bool emit(const Node& v, const Instance& I, Leaf* leaves, uint64_t cap,
+                                     Control* ctl, int round) {
   uint32_t kind;
   if (I.variant == 1)
     kind = v.Nv == 1 ? kKindFill : kKindWr;
@@ -1500,16 +1511,24 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
   // sparse and with-replacement leaves over a power-of-two range fill the
   // job array from the front, everything else from the back; the leaf
   // kernel of the other class reports the two lists meeting
-  const bool front = (kind == kKindSparse || kind == kKindWr) && (v.Nv & (v.Nv - 1)) == 0;
+  const bool front =
+      round == 0 && (kind == kKindSparse || kind == kKindWr) && (v.Nv & (v.Nv - 1)) == 0;
   // one counter word at a uniform address, so that the compiler combines
   // the wave's increments into a single atomic
   const unsigned long long old =
-      atomicAdd(&ctl->leaf_counts, front ? 1ull : static_cast<unsigned long long>(pieces) << 32);
+      atomicAdd(round == 0 ? &ctl->leaf_counts : &ctl->leaf_counts2,
+                front ? 1ull : static_cast<unsigned long long>(pieces) << 32);
+  const uint64_t asked = (old & 0xFFFFFFFFull) + (old >> 32);  // slots before this job
+  if (asked + pieces > cap) {
+    // the one job that crosses the capacity records the granted counts
+    if (asked <= cap) (round == 0 ? ctl->granted : ctl->granted2) = old;
+    return false;
+  }
   const uint64_t base = front ? (old & 0xFFFFFFFFull) : (old >> 32);
   for (uint64_t j = 0; j < pieces; ++j) {
-    if (base + j >= cap) {
+    if (base + j >= cap) {  // cannot happen: granted slots sum to at most cap
       atomicOr(ctl->err, kErrLeafCapacity);
-      return;
+      return true;
     }
     const uint64_t at = front ? base + j : cap - 1 - (base + j);
     Leaf L;
@@ -1523,6 +1542,20 @@ __device__ __forceinline__ void emit(const Node& v, const Instance& I, Leaf* lea
     L.flags = kind | (I.n0 << 8);
     leaves[at] = L;
   }
+  return true;
+}
+
+// emit, and when the job array is full: in round 0 with a redo bitmap, mark
+// tree thread t for the second round; otherwise latch the capacity error.
+__device__ __forceinline__ bool emit_or_mark(const Node& v, const Instance& I, Leaf* leaves,
+                                             uint64_t cap, Control* ctl, int round, uint32_t* redo,
+                                             uint64_t t) {
+  if (emit(v, I, leaves, cap, ctl, round)) return true;
+  if (round == 0 && redo != nullptr)
+    atomicOr(&redo[t >> 5], 1u << (t & 31u));
+  else
+    atomicOr(ctl->err, kErrLeafCapacity);
+  return false;
 }
 
 __device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t n_inst,
@@ -1540,16 +1573,18 @@ __device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t
 // early at a leaf or an empty node (the leaf is emitted by the path whose
 // remaining bits are zero).  kWave: the 64 lanes of a wave walk one path
 // together (lane 0 emits) and share each split's rejection attempts.
+// emit_or_mark's round, redo and t apply to the leaf it may emit.
 template <bool kWave = false>
 __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uint64_t g,
                                           const Instance& I, Leaf* leaves, uint64_t leaf_cap,
-                                          Control* ctl) {
+                                          Control* ctl, int round = 0, uint32_t* redo = nullptr,
+                                          uint64_t t = 0) {
   for (uint32_t d = d0; d < d1; ++d) {
     if (v.nv == 0) return false;
     if (is_leaf(v, I)) {
       const uint32_t below = d1 - d;
       if ((g & ((1ull << below) - 1)) == 0 && (!kWave || (threadIdx.x & 63u) == 0))
-        emit(v, I, leaves, leaf_cap, ctl);
+        emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t);
       return false;
     }
     const uint64_t L = split_left<kWave>(v, I);
@@ -1620,7 +1655,7 @@ __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ i
     v.off = 0;
     if (v.nv > I.part_cap) v.nv = 0;  // the caller's buffer is too small
     if (!inner) {
-      if (v.nv > 0 && g == 0 && lane0) emit(v, I, leaves, leaf_cap, ctl);
+      if (v.nv > 0 && g == 0 && lane0) emit_or_mark(v, I, leaves, leaf_cap, ctl, 0, nullptr, 0);
       v.nv = 0;
     }
     d0 = I.part_depth;
@@ -1633,9 +1668,11 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
                                               uint64_t total_threads,
                                               const Node* __restrict__ frontier, Leaf* leaves,
                                               uint64_t leaf_cap, Node* stacks,
-                                              uint32_t stack_depth, Control* ctl) {
+                                              uint32_t stack_depth, Control* ctl, uint32_t* redo,
+                                              int round) {
   const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= total_threads) return;
+  if (round == 1 && ((redo[t >> 5] >> (t & 31u)) & 1u) == 0) return;
   const uint32_t ii = find_instance(inst, n_inst, t, false);
   const Instance I = inst[ii];
   const uint64_t g = t - I.thread_base;
@@ -1643,7 +1680,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
   Node v = frontier[I.top_base + (g >> rest)];
   const uint64_t gl = g & ((1ull << rest) - 1);
   // Algorithm P: the rest of the path to this thread's depth-`cut` node.
-  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl)) return;
+  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, round, redo, t)) return;
   // Depth-first expansion of the subtree (Algorithm R below depth `cut`).
   Node* stk = stacks + t * stack_depth;
   uint32_t sp = 0;
@@ -1651,7 +1688,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     for (;;) {
       if (v.nv == 0) break;
       if (is_leaf(v, I)) {
-        emit(v, I, leaves, leaf_cap, ctl);
+        if (!emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t)) return;
         break;
       }
       const uint64_t L = split_left(v, I);
@@ -1714,14 +1751,20 @@ __global__ __launch_bounds__(256) void k_segments(Instance* inst, uint64_t K, ui
 
 __device__ inline void start_control(Control* ctl, unsigned int* err) {
   ctl->leaf_counts = 0;
+  ctl->granted = ~0ull;
+  ctl->leaf_counts2 = 0;
+  ctl->granted2 = ~0ull;
   ctl->bern_count = 0;
   ctl->error = 0;
   ctl->err = err != nullptr ? err : &ctl->error;
 }
 
 __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table,
-                        unsigned int* err) {
-  if (threadIdx.x == 0) {
+                        unsigned int* err, uint32_t* redo, uint64_t redo_words) {
+  const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < redo_words; i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    redo[i] = 0;
+  if (i0 == 0) {
     start_control(ctl, err);
     if (has_single) table[0] = single;
   }
@@ -2344,10 +2387,15 @@ hipError_t error_slots(unsigned int** out) {
 }
 
 hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
-                        hipStream_t stream) {
+                        uint32_t* redo, uint64_t redo_words, hipStream_t stream) {
   Instance one{};
   if (single) one = *single;
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, ctl, one, single ? 1 : 0, table, err);
+  if (redo == nullptr) redo_words = 0;
+  uint64_t blocks = (redo_words + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_reset, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, one,
+                     single ? 1 : 0, table, err, redo, redo_words);
   return hipGetLastError();
 }
 
@@ -2425,11 +2473,14 @@ hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_t
 
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
-                       uint32_t stack_depth, Control* ctl, hipStream_t stream) {
+                       uint32_t stack_depth, Control* ctl, uint32_t* redo, int round,
+                       hipStream_t stream) {
   if (total_threads == 0) return hipSuccess;
+  if (round != 0 && redo == nullptr) return hipErrorInvalidValue;
   const uint64_t blocks = (total_threads + 255) / 256;
   hipLaunchKernelGGL(k_tree, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
-                     n_inst, total_threads, frontier, leaves, leaf_cap, stacks, stack_depth, ctl);
+                     n_inst, total_threads, frontier, leaves, leaf_cap, stacks, stack_depth, ctl,
+                     redo, round);
   return hipGetLastError();
 }
 
@@ -2440,7 +2491,14 @@ hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, ui
                        leaf_cap, out, ctl);
   else
     hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
-                       leaf_cap, out, ctl);
+                       leaf_cap, out, ctl, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                              uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
+                     leaf_cap, out, ctl, 1);
   return hipGetLastError();
 }
 

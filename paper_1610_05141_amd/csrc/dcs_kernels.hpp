@@ -61,18 +61,29 @@ struct Control {
   // with-replacement leaves over power-of-two ranges (filled from the front
   // of the job array),
   // high 32 bits all others (filled from the back); one 64-bit atomic
-  // serves both
+  // serves both.  Jobs that did not fit count too (see `granted`).
   unsigned long long leaf_counts;
   // where the kernels latch error bits (kErr*): a library-owned word of the
   // launch stream, or `error` below when the caller reads the block itself
   // (the serving loop); set by k_reset / k_zero at the start of every call
   unsigned int* err;
-  unsigned long long pad1;
+  // ~0, or leaf_counts just before the first job whose slots did not fit:
+  // a job gets its slots iff the slots asked for up to it (front and back
+  // together, in the order of the atomic) fit the capacity, so the granted
+  // jobs are those counted here and they never overlap.  Every tree thread
+  // stops at its first job that does not fit, so the counts stay far below
+  // 2^32 (capacity plus threads).
+  unsigned long long granted;
   unsigned int error;              // this call's own error bits (see `err`)
   unsigned int pad;
   unsigned long long bern_count;   // Bernoulli: total hits (copied to the caller)
+  // second round (tree threads whose leaves did not all get a slot, run
+  // again): its jobs, all on the back list, as leaf_counts and granted
+  unsigned long long leaf_counts2;
+  unsigned long long granted2;
+  unsigned long long pad2;
 };
-static_assert(sizeof(Control) == 40, "control block layout");
+static_assert(sizeof(Control) == 64, "control block layout");
 
 // Library-owned error words, one per stream that has launched work (the
 // last one shared by streams beyond kErrSlots - 1), per device: kept in
@@ -105,8 +116,10 @@ constexpr uint32_t kTicketWords = kTicketClasses * kTicketStride;
 // and point its kernels' error latch at `err` (nullptr: at the block's own
 // error word); if `single` is non-null, also store that instance as entry 0
 // of the instance table.
+// redo (may be null): the second round's bitmap over tree threads, redo_words
+// 32-bit words, zeroed here too.
 hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
-                        hipStream_t stream);
+                        uint32_t* redo, uint64_t redo_words, hipStream_t stream);
 // launch_reset for a Bernoulli call plus zeroing of its look-back status words
 // and its kTicketWords chunk counters.
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
@@ -128,14 +141,27 @@ int bern_wave_occupancy();
 hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_threads,
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
                            uint64_t* part_out, hipStream_t stream);
+// Below the frontier.  redo == null: a leaf that finds the job array full
+// latches kErrLeafCapacity.  Otherwise round 0 marks its thread in the redo
+// bitmap instead (the thread stops; the leaves it did hand over are sampled
+// by the first leaf pass), and round 1 runs only the marked threads again,
+// from their frontier node, into the emptied job array (every job on the
+// back list), latching kErrLeafCapacity if that does not fit either.  A
+// leaf's values go to fixed places of the output, so a leaf handed over in
+// both rounds is written twice with the same values.
 hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_threads,
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
-                       uint32_t stack_depth, Control* ctl, hipStream_t stream);
+                       uint32_t stack_depth, Control* ctl, uint32_t* redo, int round,
+                       hipStream_t stream);
 // Leaf kernel over one of the two job lists: pow2_list = the front list
 // (sparse and with-replacement leaves over power-of-two ranges), else the
 // back list (all others).
 hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream);
+// The second round's jobs (all on the back list, every kind run by the
+// work-group bodies); returns at once when round 0 handed over every leaf.
+hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
+                              uint32_t grid, hipStream_t stream);
 // Dense leaves of the back list whose range fits 16-bit positions, one wave
 // per leaf (k_leaf_mixed skips them).
 hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,

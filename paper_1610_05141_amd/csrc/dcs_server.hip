@@ -184,6 +184,7 @@ bool dcs_server::launch_batch() {
   std::vector<Instance> inst;
   uint64_t threads = 0, top_threads = 0, leaf_cap = 0, total_n = 0;
   uint32_t stack_depth = 1;
+  bool second_round = false;
   inst.reserve(batch.size());
   for (uint64_t tk : batch) {
     const Req& R = reqs[tk];
@@ -206,11 +207,13 @@ bool dcs_server::launch_batch() {
     threads += pl.threads;
     top_threads += pl.threads ? pl.top_threads : 0;
     leaf_cap += pl.leaf_cap;
+    second_round = second_round || pl.second_round;
     stack_depth = std::max(stack_depth, pl.stack_depth);
     inst.push_back(I);
   }
   const uint32_t n_inst = static_cast<uint32_t>(inst.size());
-  const TreeLayout L = dcs::host::tree_layout(n_inst, leaf_cap, threads, stack_depth, top_threads);
+  const TreeLayout L =
+      dcs::host::tree_layout(n_inst, leaf_cap, threads, stack_depth, top_threads, second_round);
   if (sl->ws_bytes < L.total) {
     if (sl->ws) {
       if (hipStreamSynchronize(sl->stream) != hipSuccess || hipFree(sl->ws) != hipSuccess) {
