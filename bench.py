@@ -338,6 +338,50 @@ def bench_parts(dcs, depths=(4, 8), reps: int = 3):
         }
         del buf
         torch.cuda.empty_cache()
+    # Sessions: the part roots computed once, then runs of `run` consecutive
+    # parts per call into one reused buffer (its size: the largest run).
+    for d, run in ((8, 1), (8, 16), (12, 256)):
+        t0 = time.perf_counter()
+        o = dcs.Online(n, N, seed, d, n0=N0, stream=stream)
+        create_ms = (time.perf_counter() - t0) * 1e3
+        counts, _ = o.counts()
+        cap = max(int(counts[g:g + run].sum()) for g in range(0, 1 << d, run))
+        buf = torch.empty(cap, dtype=torch.int64, device="cuda")
+
+        def sweep():
+            total = 0
+            for g in range(0, 1 << d, run):
+                total += o.next(g, run, buf, stream=stream)
+            return total
+
+        sweep()
+        dcs.synchronize(stream)
+        dcs.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            total = sweep()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / reps
+        t_ms, t_n = dcs.profile_read(1)
+        l_ms, l_n = dcs.profile_read(2)
+        dcs.profile_enable(False)
+        calls = (1 << d) // run
+        res[f"session_depth_{d}_run_{run}"] = {
+            "parts": 1 << d,
+            "parts_per_call": run,
+            "buffer_bytes": 8 * cap,
+            "create_ms": create_ms,
+            "ms_all_parts": dt * 1e3,
+            "ms_per_call": dt * 1e3 / calls,
+            "samples_per_s": n / dt,
+            "tree_ms_per_call": t_ms / max(t_n, 1),
+            "leaf_ms_per_call": l_ms / max(l_n, 1),
+            "vs_one_call": plain_ms / (dt * 1e3),
+            "all_values": total == n,
+        }
+        o.close()
+        del buf
+        torch.cuda.empty_cache()
     return res
 
 

@@ -181,6 +181,42 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
                         void* stream);
 
 /*
+ * dcs_online_* -- online sampling in sorted order (Sec. 4.1), as a session:
+ * the sample of dcs_sample (variant 0) or dcs_sample_replacement (variant 1)
+ * for (n, N, seed, params), cut into the 2^depth parts of dcs_sample_part,
+ * produced in runs of consecutive parts with bounded memory.
+ * dcs_online_create computes the roots of all parts at once on the device
+ * (one thread per part walks the splits above it; Sec. 3.2: every split
+ * depends only on its node's identity) and copies their counts and ranks
+ * to the host; it synchronizes `stream` before returning.  Afterwards no
+ * split above the cut is computed again: dcs_online_next samples parts
+ * [first, first + count) from their roots, concatenated (their values
+ * ascending) into out_dev[0 .. written), in one launch sequence on
+ * `stream`, so the cost of a call follows the values it produces.
+ *   counts, ranks (host, may be NULL): count values of the parts' sizes and
+ *                  ranks (where each part starts in the full sample).
+ *   written (host, may be NULL): the number of values of the requested
+ *                  parts; known on the host, so the caller sizes the next
+ *                  call without synchronizing.
+ * Errors: DCS_EINVAL for the argument errors of dcs_sample_part, depth >
+ * DCS_MAX_ONLINE_DEPTH, a NULL session or out_dev (with values to write),
+ * or parts beyond 2^depth; DCS_ENOMEM (nothing enqueued) if the parts hold
+ * more than `capacity` values.  dcs_online_next uses the library's
+ * workspace (as dcs_sample does); a session holds 40 B of host memory per
+ * part and no device memory.
+ */
+#define DCS_MAX_ONLINE_DEPTH 20
+typedef struct dcs_online dcs_online; /* opaque */
+int32_t dcs_online_create(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
+                          const dcs_params* params, uint32_t depth, void* stream,
+                          dcs_online** online);
+int32_t dcs_online_counts(const dcs_online* online, uint64_t first, uint64_t count,
+                          uint64_t* counts, uint64_t* ranks);
+int32_t dcs_online_next(dcs_online* online, uint64_t first, uint64_t count, uint64_t* out_dev,
+                        uint64_t capacity, uint64_t* written, void* stream);
+int32_t dcs_online_destroy(dcs_online* online);
+
+/*
  * dcs_sample_edges_gnm -- the edges of a uniform random graph G(n, m) on the
  * vertices 0..n_vertices-1 (Sec. 7: such a graph is a sample without
  * replacement of m of the n(n-1)/2 possible edges).  Edge index k (0-based)

@@ -16,8 +16,9 @@ __all__ = [
     "DcsError", "lib", "sample", "sample_noalloc", "sample_replacement", "sample_bernoulli", "sample_part",
     "sample_segments", "sample_wholerange", "sample_edges_gnm", "sample_edges_gnp",
     "synchronize",
-    "workspace_size", "bernoulli_capacity_hint", "Batch", "Server", "profile_enable",
-    "profile_read", "profile_kinds", "debug_primitive", "tune_set", "tune_get", "tune_reset",
+    "workspace_size", "bernoulli_capacity_hint", "Batch", "Online", "Server", "profile_enable",
+    "profile_read", "profile_kinds", "debug_primitive", "debug_plan", "debug_leaf_capacity",
+    "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
 
@@ -39,7 +40,8 @@ EXPORTED_SYMBOLS = (
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
     "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset", "dcs_debug_leaf_capacity",
-    "dcs_debug_plan",
+    "dcs_debug_plan", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
+    "dcs_online_destroy",
 )
 
 
@@ -132,6 +134,10 @@ def lib() -> ctypes.CDLL:
             "dcs_tune_reset": (i32, []),
             "dcs_debug_leaf_capacity": (i32, [u64, i32, ctypes.POINTER(u32)]),
             "dcs_debug_plan": (i32, [i32, u64, u64, pp, ctypes.POINTER(u64)]),
+            "dcs_online_create": (i32, [i32, u64, u64, u64, pp, u32, vp, ctypes.POINTER(vp)]),
+            "dcs_online_counts": (i32, [vp, u64, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+            "dcs_online_next": (i32, [vp, u64, u64, vp, u64, ctypes.POINTER(u64), vp]),
+            "dcs_online_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -342,6 +348,54 @@ class InstanceSpec:
     variant: int = 0
     n0: int = 0
     dense_ratio: int = 0
+
+
+class Online:
+    """Online sampling in sorted order (Sec. 4.1): the sample of `sample`
+    (variant 0) or `sample_replacement` (variant 1) as the 2^depth parts of
+    the depth-`depth` cut, whose roots are computed once, produced in runs of
+    consecutive parts."""
+
+    def __init__(self, n: int, N: int, seed: int, depth: int, variant: int = 0, n0=None,
+                 dense_ratio=None, stream=None):
+        self.depth = depth
+        self.parts = 1 << depth
+        h = ctypes.c_void_p()
+        _check(lib().dcs_online_create(variant, n, N, seed, _params(n0, dense_ratio), depth,
+                                       _stream_handle(stream), ctypes.byref(h)),
+               "dcs_online_create")
+        self._h = h
+
+    def counts(self, first: int = 0, count=None):
+        """(counts, ranks) of parts [first, first + count) as numpy arrays."""
+        import numpy as np
+        count = self.parts - first if count is None else count
+        c = np.zeros(max(count, 1), dtype=np.uint64)
+        r = np.zeros(max(count, 1), dtype=np.uint64)
+        _check(lib().dcs_online_counts(self._h, first, count,
+                                       c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                       r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+               "dcs_online_counts")
+        return c[:count], r[:count]
+
+    def next(self, first: int, count: int, out, stream=None) -> int:
+        """Parts [first, first + count) into out (a device int64 tensor);
+        returns the number of values written."""
+        w = ctypes.c_uint64(0)
+        _check(lib().dcs_online_next(self._h, first, count, _ptr(out), out.numel(),
+                                     ctypes.byref(w), _stream_handle(stream)), "dcs_online_next")
+        return int(w.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().dcs_online_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

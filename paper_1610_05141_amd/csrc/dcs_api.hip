@@ -1047,6 +1047,146 @@ int32_t dcs_batch_destroy(dcs_batch* b) {
   return DCS_OK;
 }
 
+// ---- online sampling -------------------------------------------------------
+}  // extern "C"
+
+struct dcs_online {
+  int32_t variant = 0;
+  uint64_t n = 0, N = 0, seed = 0;
+  Params P;
+  uint32_t depth = 0;
+  std::vector<Node> roots;  // part g: its root node, off = its rank
+  std::vector<Instance> tab;
+};
+
+extern "C" {
+
+int32_t dcs_online_create(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
+                          const dcs_params* params, uint32_t depth, void* stream,
+                          dcs_online** online) {
+  if (online == nullptr) return DCS_EINVAL;
+  *online = nullptr;
+  Params P;
+  if (read_params(params, &P) != DCS_OK) return DCS_EINVAL;
+  if (variant != 0 && variant != 1) return DCS_EINVAL;
+  if (N > DCS_MAX_UNIVERSE || depth > DCS_MAX_ONLINE_DEPTH) return DCS_EINVAL;
+  if (variant == 0 && n > N) return DCS_EINVAL;
+  if (variant == 1 && N == 0 && n > 0) return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  auto* o = new dcs_online();
+  o->variant = variant;
+  o->n = n;
+  o->N = N;
+  o->seed = seed;
+  o->P = P;
+  o->depth = depth;
+  const uint64_t parts = 1ull << depth;
+  o->roots.assign(parts, Node{0, 0, 0, 0, 0});
+  if (n > 0) {
+    Instance I{};
+    I.n = n;
+    I.N = N;
+    I.seed = seed;
+    I.n0 = P.n0;
+    I.dense_ratio = P.dense_ratio;
+    I.variant = static_cast<uint32_t>(variant);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    rc = own_workspace(c, sizeof(Node) * parts, &ws);
+    if (rc == DCS_OK) {
+      Node* dev = static_cast<Node*>(ws);
+      if (dcs::launch_part_roots(I, depth, dev, s) != hipSuccess ||
+          hipMemcpyAsync(o->roots.data(), dev, sizeof(Node) * parts, hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        rc = DCS_EHIP;
+    }
+    if (rc) {
+      delete o;
+      return rc;
+    }
+  }
+  *online = o;
+  return DCS_OK;
+}
+
+int32_t dcs_online_counts(const dcs_online* o, uint64_t first, uint64_t count, uint64_t* counts,
+                          uint64_t* ranks) {
+  if (o == nullptr || first > o->roots.size() || count > o->roots.size() - first) return DCS_EINVAL;
+  for (uint64_t i = 0; i < count; ++i) {
+    const Node& v = o->roots[first + i];
+    if (counts) counts[i] = v.nv;
+    if (ranks) ranks[i] = v.off;
+  }
+  return DCS_OK;
+}
+
+int32_t dcs_online_next(dcs_online* o, uint64_t first, uint64_t count, uint64_t* out_dev,
+                        uint64_t capacity, uint64_t* written, void* stream) {
+  if (o == nullptr || first > o->roots.size() || count > o->roots.size() - first) return DCS_EINVAL;
+  uint64_t total = 0;
+  for (uint64_t i = 0; i < count; ++i) total += o->roots[first + i].nv;
+  if (written) *written = total;
+  if (total > capacity) return DCS_ENOMEM;
+  if (total == 0) return DCS_OK;
+  if (out_dev == nullptr) return DCS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* c;
+  int32_t rc = device_ctx(&c);
+  if (rc) return rc;
+  // every non-empty part is an instance rooted at its node of the whole tree
+  const uint64_t rank0 = o->roots[first].off;
+  std::vector<Instance>& tab = o->tab;
+  tab.clear();
+  uint64_t tb = 0, tt = 0, leaf_cap = 0;
+  uint32_t stack_depth = 1;
+  bool second = false;
+  const uint32_t v = static_cast<uint32_t>(o->variant);
+  for (uint64_t i = 0; i < count; ++i) {
+    const Node& r = o->roots[first + i];
+    if (r.nv == 0) continue;
+    const Plan pl = make_plan(r.nv, r.Nv, o->P.n0, v, cut_bias_for(v, r.nv));
+    Instance I{};
+    I.n = r.nv;
+    I.N = r.Nv;
+    I.base = r.lo;
+    I.root = r.id;
+    I.seed = o->seed;
+    I.out_offset = r.off - rank0;
+    I.thread_base = tb;
+    I.top_base = tt;
+    I.n0 = o->P.n0;
+    I.dense_ratio = o->P.dense_ratio;
+    I.variant = v;
+    I.cut = pl.cut;
+    I.top_cut = pl.top_cut;
+    tb += pl.threads;
+    tt += pl.top_threads;
+    leaf_cap += pl.leaf_cap;
+    second = second || pl.second_round;
+    stack_depth = std::max(stack_depth, pl.stack_depth);
+    tab.push_back(I);
+  }
+  const uint32_t n_inst = static_cast<uint32_t>(tab.size());
+  const TreeLayout L = tree_layout(n_inst, leaf_cap, tb, stack_depth, tt, second);
+  void* ws = nullptr;
+  rc = own_workspace(c, L.total, &ws);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = stage_upload(c, tab.data(), sizeof(Instance) * n_inst, static_cast<char*>(ws) + L.inst, s);
+  if (rc) return rc;
+  return run_tree_pipeline(c, ws, L, nullptr, n_inst, tb, tt, leaf_cap, stack_depth, out_dev, s,
+                           error_word(c, stream), leaf_wgs_for(c, v, total));
+}
+
+int32_t dcs_online_destroy(dcs_online* o) {
+  delete o;
+  return DCS_OK;
+}
+
 // ---- status, timing, diagnostics -------------------------------------------
 int32_t dcs_synchronize(void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);

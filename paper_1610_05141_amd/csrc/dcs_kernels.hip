@@ -1605,7 +1605,9 @@ __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uin
 // leaves the other parts empty, with rank after the leaf's values; an empty
 // node gives an empty part.  On return v.nv is the part's count and v.off
 // its rank (values of the sample in earlier parts); returns false when the
-// part is a leaf above dp or empty.
+// part is a leaf above dp or empty.  kWave: the wave's 64 lanes walk this
+// path together (sharing each split's rejection attempts).
+template <bool kWave = true>
 __device__ __forceinline__ bool part_root(Node& v, uint32_t dp, uint64_t part,
                                           const Instance& I) {
   for (uint32_t d = 0; d < dp; ++d) {
@@ -1618,7 +1620,7 @@ __device__ __forceinline__ bool part_root(Node& v, uint32_t dp, uint64_t part,
       }
       return false;
     }
-    const uint64_t L = split_left<true>(v, I);
+    const uint64_t L = split_left<kWave>(v, I);
     const uint64_t l = v.Nv >> 1;
     if ((part >> (dp - 1 - d)) & 1) {
       v = Node{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
@@ -1644,7 +1646,7 @@ __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ i
   const Instance I = inst[find_instance(inst, n_inst, t, true)];
   const uint64_t g = t - I.top_base;
   const bool lane0 = (threadIdx.x & 63u) == 0;
-  Node v{1, I.base, I.N, I.n, 0};
+  Node v{I.root ? I.root : 1, I.base, I.N, I.n, 0};
   uint32_t d0 = 0;
   if (part_out != nullptr) {
     const bool inner = part_root(v, I.part_depth, I.part, I);
@@ -1706,6 +1708,19 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     if (sp == 0) break;
     v = stk[--sp];
   }
+}
+
+// Online sampling (Sec. 4.1): the roots of all parts of a depth-dp cut at
+// once, one thread per part walking its own path from the root (part_root's
+// rule for leaves above the cut and for empty nodes), so that later calls
+// sample parts from their roots without recomputing the splits above.
+__global__ __launch_bounds__(256) void k_part_roots(Instance I, uint32_t dp, uint64_t parts,
+                                                    Node* roots) {
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= parts) return;
+  Node v{1, I.base, I.N, I.n, 0};
+  part_root<false>(v, dp, g, I);
+  roots[g] = v;
 }
 
 // Uneven universe (Sec. 4.3): thread i follows the binomial tree of the K
@@ -2499,6 +2514,14 @@ hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* o
                               uint32_t grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                      leaf_cap, out, ctl, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_roots(const Instance& I, uint32_t depth, Node* roots, hipStream_t stream) {
+  const uint64_t parts = 1ull << depth;
+  const uint64_t blocks = (parts + 255) / 256;
+  hipLaunchKernelGGL(k_part_roots, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, I,
+                     depth, parts, roots);
   return hipGetLastError();
 }
 

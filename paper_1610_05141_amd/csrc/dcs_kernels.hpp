@@ -27,8 +27,12 @@ struct Instance {
   uint64_t part;
   uint64_t part_cap;    // nothing is sampled if the part holds more values
   // Elements before this instance's range: its root covers base+1 .. base+N
-  // (0 except for the segments of an uneven universe).
+  // (0 except for the segments of an uneven universe and online parts).
   uint64_t base;
+  // Node id of the instance's root in the tree of its seed: 0 stands for 1,
+  // the whole tree; an online part's subtree keeps the id its root has in
+  // the whole sample's tree, so its splits and leaves are the same.
+  uint64_t root;
 };
 
 // A recursion-tree node (Fig. 1): node id (root 1, children 2i, 2i+1), the
@@ -175,6 +179,10 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,
                             uint64_t* count_dev, Control* ctl, unsigned long long* tickets,
                             uint32_t grid, uint32_t lds_cap, hipStream_t stream);
+// Online sampling: the 2^depth part roots of instance I's depth-`depth` cut
+// (node with off = the part's rank; an empty part has nv = 0, a leaf above
+// the cut goes whole to the leftmost part below it).
+hipError_t launch_part_roots(const Instance& I, uint32_t depth, Node* roots, hipStream_t stream);
 // Uneven universe: fills count, seed and output offset of the K segment
 // instances (their base and N set) from the splits of the binomial tree of
 // depth D over them; counts (may be null) receives the K counts.
