@@ -469,10 +469,11 @@ const char* dcs_status_string(int32_t status);
  * launched on.  enable != 0 starts recording (and clears the totals).
  * dcs_profile_read: after the stream is synchronized, accumulated
  * milliseconds and launch count for kernel `kind`
- * (0 = reset, 1 = tree split, 2 = leaf stage: all three leaf kernels,
+ * (0 = reset, 1 = tree split, 2 = leaf stage: all leaf kernels,
  * 3 = Bernoulli chunk, 4 = leaf kernel of the sparse and with-replacement
  * jobs over power-of-two ranges,
- * 5 = work-group leaf kernel of the other jobs, 6 = one-wave-per-leaf
+ * 5 = work-group leaf kernel of the other jobs and of the second round's
+ * jobs, 6 = one-wave-per-leaf
  * kernel of the dense jobs with ranges up to 2^16, 7 = edge-index
  * decoding of the graph entry points, 8 = the segment splits of
  * dcs_sample_segments, 9 / 10 / 11 = the count passes / the scan and

@@ -435,7 +435,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   uint32_t* redo = L.redo_words ? reinterpret_cast<uint32_t*>(base + L.redo) : nullptr;
   Timing t0{}, t1{}, t2{};
   timing_begin(0, s, &t0);
-  hipError_t e = dcs::launch_reset(ctl, single, inst, err, redo, L.redo_words, s);
+  hipError_t e = dcs::launch_reset(ctl, single, inst, err, redo, L.redo_words, out, s);
   timing_end(s, &t0);
   if (e != hipSuccess) return DCS_EHIP;
   timing_begin(1, s, &t1);

@@ -1308,8 +1308,9 @@ __device__ __forceinline__ uint64_t job_counts(const Control* ctl, int round) {
 // kPow2: the front list (sparse and with-replacement leaves over power-of-two
 // ranges) with only that leaf body compiled in, so that the hot path keeps
 // its values in registers; otherwise the back list with every other leaf
-// body.  round2: the second round's jobs (back list only, every kind, none
-// left to the one-wave kernels).
+// body, leaving to the one-wave kernels the jobs they take.  round2: the
+// second round's jobs (back list only, every kind, none left to the one-wave
+// kernels).
 template <int B, bool kPow2>
 __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
                                           uint64_t* out, Control* ctl, int round2 = 0) {
@@ -1374,7 +1375,7 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
         }
         __syncthreads();
         keep = __builtin_amdgcn_readfirstlane(sm.scr[kScrKeep]);
-        if (keep == 0) {  // the whole group is k_leaf_dense's
+        if (keep == 0) {  // the whole group is the one-wave kernels'
           j += kCacheLeaves - 1;
           continue;
         }
@@ -1496,6 +1497,59 @@ __device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I)
                         : hypergeometric<kWave>(v.nv, l, v.Nv, I.seed, v.id);
 }
 
+// Leaves of at most kInlineMax values, sparse or with replacement, are
+// sampled by the tree thread that reaches them, straight into the output:
+// the values the leaf kernels would give (the first n_v distinct non-void
+// values of the leaf's word stream mapped into [0, N_v), or with replacement
+// its first n_v non-void values with repeats, ascending), without a job.
+constexpr uint32_t kInlineMax = 4;
+
+__device__ __forceinline__ bool leaf_inline_kind(const Node& v, const Instance& I) {
+  if (v.nv > kInlineMax) return false;
+  if (I.variant == 1) return v.Nv != 1;  // constant leaves stay jobs
+  return static_cast<uint64_t>(I.dense_ratio) * v.nv < v.Nv;  // sparse (dense stay jobs)
+}
+
+__device__ void leaf_inline(const Node& v, const Instance& I, uint64_t* out) {
+  const bool wr = I.variant == 1;
+  const Stream st = make_stream(I.seed, v.id, wr ? kWrLeaf : kLeaf, 0);
+  const uint32_t thr = range_threshold(v.Nv);
+  const uint32_t nv = static_cast<uint32_t>(v.nv);
+  // values kept so far, in stream order; unused slots hold the largest word
+  uint32_t k0 = ~0u, k1 = ~0u, k2 = ~0u, k3 = ~0u;
+  uint32_t have = 0;
+  for (uint64_t blk = 0; have < nv; ++blk) {
+    const uint4 w = philox_block(st, blk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t x;
+      const bool ok = range_map(pick(w, j), v.Nv, thr, &x) && have < nv;
+      const bool dup = !wr && ((have > 0 && x == k0) || (have > 1 && x == k1) ||
+                               (have > 2 && x == k2));
+      if (ok && !dup) {
+        k0 = have == 0 ? x : k0;
+        k1 = have == 1 ? x : k1;
+        k2 = have == 2 ? x : k2;
+        k3 = have == 3 ? x : k3;
+        ++have;
+      }
+    }
+  }
+  // ascending (five comparators sort four values)
+  uint32_t a, b;
+  a = min(k0, k1); b = max(k0, k1); k0 = a; k1 = b;
+  a = min(k2, k3); b = max(k2, k3); k2 = a; k3 = b;
+  a = min(k0, k2); b = max(k0, k2); k0 = a; k2 = b;
+  a = min(k1, k3); b = max(k1, k3); k1 = a; k3 = b;
+  a = min(k1, k2); b = max(k1, k2); k1 = a; k2 = b;
+  uint64_t* o = out + I.out_offset + v.off;
+  const uint64_t b1 = v.lo + 1;
+  store_out(o, b1 + k0);
+  if (nv > 1) store_out(o + 1, b1 + k1);
+  if (nv > 2) store_out(o + 2, b1 + k2);
+  if (nv > 3) store_out(o + 3, b1 + k3);
+}
+
 // Hand leaf v over as a job (round 0: front or back list by kind; round 1:
 // back list).  The job's slots are granted iff the slots asked for so far,
 // these included, fit the capacity; returns whether they were.
@@ -1550,6 +1604,10 @@ __device__ __forceinline__ bool emit(const Node& v, const Instance& I, Leaf* lea
 __device__ __forceinline__ bool emit_or_mark(const Node& v, const Instance& I, Leaf* leaves,
                                              uint64_t cap, Control* ctl, int round, uint32_t* redo,
                                              uint64_t t) {
+  if (leaf_inline_kind(v, I)) {
+    leaf_inline(v, I, ctl->out);
+    return true;
+  }
   if (emit(v, I, leaves, cap, ctl, round)) return true;
   if (round == 0 && redo != nullptr)
     atomicOr(&redo[t >> 5], 1u << (t & 31u));
@@ -1684,7 +1742,9 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
   // Algorithm P: the rest of the path to this thread's depth-`cut` node.
   if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, round, redo, t)) return;
   // Depth-first expansion of the subtree (Algorithm R below depth `cut`).
-  Node* stk = stacks + t * stack_depth;
+  // Entry k of thread t's stack is stacks[k * total_threads + t], so that the
+  // pushes of a wave's threads at one level share cache lines.
+  Node* stk = stacks + t;
   uint32_t sp = 0;
   for (;;) {
     for (;;) {
@@ -1701,12 +1761,12 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
           atomicOr(ctl->err, kErrStackDepth);
           return;
         }
-        stk[sp++] = right;
+        stk[static_cast<uint64_t>(sp++) * total_threads] = right;
       }
       v = Node{2 * v.id, v.lo, l, L, v.off};
     }
     if (sp == 0) break;
-    v = stk[--sp];
+    v = stk[static_cast<uint64_t>(--sp) * total_threads];
   }
 }
 
@@ -1769,18 +1829,20 @@ __device__ inline void start_control(Control* ctl, unsigned int* err) {
   ctl->granted = ~0ull;
   ctl->leaf_counts2 = 0;
   ctl->granted2 = ~0ull;
+  ctl->out = nullptr;
   ctl->bern_count = 0;
   ctl->error = 0;
   ctl->err = err != nullptr ? err : &ctl->error;
 }
 
 __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance* table,
-                        unsigned int* err, uint32_t* redo, uint64_t redo_words) {
+                        unsigned int* err, uint32_t* redo, uint64_t redo_words, uint64_t* out) {
   const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   for (uint64_t i = i0; i < redo_words; i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
     redo[i] = 0;
   if (i0 == 0) {
     start_control(ctl, err);
+    ctl->out = out;
     if (has_single) table[0] = single;
   }
 }
@@ -2402,7 +2464,7 @@ hipError_t error_slots(unsigned int** out) {
 }
 
 hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
-                        uint32_t* redo, uint64_t redo_words, hipStream_t stream) {
+                        uint32_t* redo, uint64_t redo_words, uint64_t* out, hipStream_t stream) {
   Instance one{};
   if (single) one = *single;
   if (redo == nullptr) redo_words = 0;
@@ -2410,7 +2472,7 @@ hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, u
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_reset, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, ctl, one,
-                     single ? 1 : 0, table, err, redo, redo_words);
+                     single ? 1 : 0, table, err, redo, redo_words, out);
   return hipGetLastError();
 }
 

@@ -85,7 +85,9 @@ struct Control {
   // again): its jobs, all on the back list, as leaf_counts and granted
   unsigned long long leaf_counts2;
   unsigned long long granted2;
-  unsigned long long pad2;
+  // the call's output (tree calls): the tree kernels write leaves of a few
+  // values themselves
+  uint64_t* out;
 };
 static_assert(sizeof(Control) == 64, "control block layout");
 
@@ -121,9 +123,9 @@ constexpr uint32_t kTicketWords = kTicketClasses * kTicketStride;
 // error word); if `single` is non-null, also store that instance as entry 0
 // of the instance table.
 // redo (may be null): the second round's bitmap over tree threads, redo_words
-// 32-bit words, zeroed here too.
+// 32-bit words, zeroed here too.  out: the call's output.
 hipError_t launch_reset(Control* ctl, const Instance* single, Instance* table, unsigned int* err,
-                        uint32_t* redo, uint64_t redo_words, hipStream_t stream);
+                        uint32_t* redo, uint64_t redo_words, uint64_t* out, hipStream_t stream);
 // launch_reset for a Bernoulli call plus zeroing of its look-back status words
 // and its kTicketWords chunk counters.
 hipError_t launch_zero(Control* ctl, unsigned long long* status, uint64_t n,
@@ -159,7 +161,7 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
                        hipStream_t stream);
 // Leaf kernel over one of the two job lists: pow2_list = the front list
 // (sparse and with-replacement leaves over power-of-two ranges), else the
-// back list (all others).
+// back list's jobs that the one-wave kernels do not take.
 hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream);
 // The second round's jobs (all on the back list, every kind run by the

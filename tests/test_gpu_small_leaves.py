@@ -57,3 +57,32 @@ def test_small_leaf_kernel_runs(ref):
     m.profile_enable(False)
     assert small_n == 1 and small_ms > 0
     assert mixed_ms < small_ms
+
+
+TINY = [
+    # (variant, n, N, seed, n0): leaves of one to a few values, which the tree
+    # kernel samples itself (the range bound forces depth ~30 here)
+    (0, 300_000, 1 << 60, 31, None),
+    (0, 200_000, (1 << 58) + 12345, 32, None),   # ranges that are not powers of two
+    (1, 250_000, (1 << 55) + 7, 33, None),
+    (0, 60_000, 1 << 40, 34, 3),                  # n0 = 3: leaves of 1 or 2 values
+    (1, 80_000, 1 << 20, 35, 4),                  # with replacement: repeats inside tiny leaves
+    (0, 5_000, 1 << 16, 36, 2),                   # leaves of one value; dense ones stay jobs
+]
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_tiny_leaves_bitexact(ref, case):
+    variant, n, N, seed, n0 = TINY[case]
+    m = dcs()
+    kw = {} if n0 is None else {"n0": n0}
+    if variant == 0:
+        _, leaves, _ = ref.tree_stats(n, N, seed, **kw)
+        assert n / leaves <= 4, (leaves, n / leaves)
+    announce(f"tiny leaves case {case}: variant={variant} n={n} N={N} seed={seed} n0={n0}")
+    f = m.sample if variant == 0 else m.sample_replacement
+    out = f(n, N, seed, **kw)
+    m.synchronize()
+    got = to_np_u64(out)
+    want = (ref.sample if variant == 0 else ref.replacement)(n, N, seed, **kw)
+    assert np.array_equal(got, want), first_mismatch(got, want)
