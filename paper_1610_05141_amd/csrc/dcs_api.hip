@@ -29,7 +29,7 @@ using dcs::Node;
 
 constexpr uint32_t kDefaultN0 = 4096;
 constexpr uint32_t kDefaultDenseRatio = 16;
-constexpr uint32_t kMaxCut = 18;
+constexpr uint32_t kMaxCut = 20;
 constexpr size_t kAlign = 256;
 // A leaf's range must fit a 32-bit draw (the tree splits larger ranges).
 constexpr uint64_t kLeafRange = 1ull << 32;
@@ -68,19 +68,26 @@ int32_t read_params(const dcs_params* p, Params* out) {
 uint64_t sat_add(uint64_t a, uint64_t b) { return a + b < a ? ~0ull : a + b; }
 
 // Leaf jobs of the canonical tree, bounded for every outcome of its random
-// splits.  Every job is a non-empty child of an internal node, the root, or
-// an extra piece of a constant leaf (at most n / kFillPiece of those), so
-// there are at most 2 I + 1 + n / kFillPiece, and at most n (each holds a
-// value).  I counts internal nodes level by level: at depth d at most 2^d
-// nodes, and at most n, are non-empty; where no range exceeds 2^32 a node
-// splits only if it holds n0 or more values, and at most n / n0 such nodes
-// are disjoint.  Without replacement that needs N_v >= n_v >= n0, with
-// replacement N_v >= 2, which ends the levels.
-uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
+// splits.  Every leaf is a non-empty child of an internal node or the root,
+// so there are at most 2 I + 1 leaves, and at most n (each holds a value).
+// I counts internal nodes level by level: at depth d at most 2^d nodes, and
+// at most n, are non-empty; where no range exceeds 2^32 a node splits only
+// if it holds n0 or more values, and at most n / n0 such nodes are disjoint.
+// Without replacement that needs N_v >= n_v >= n0, with replacement
+// N_v >= 2, which ends the levels at depth d_last.  Jobs: leaves the tree
+// kernels do not sample themselves, plus the extra pieces of constant
+// leaves (at most n / kFillPiece).  Without replacement, when no leaf can
+// span dense_ratio * kInlineMax elements or fewer (leaves lie at depth
+// d_last + 1 or above, so they span at least floor(N / 2^(d_last + 1))),
+// every leaf of at most kInlineMax values is sparse and sampled by the tree,
+// so jobs hold at least kInlineMax + 1 values each: at most
+// n / (kInlineMax + 1) of them.
+uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t dense_ratio, uint32_t variant) {
   if (n == 0) return 0;
   const uint64_t need = variant == 0 ? n0 : 2;
   uint64_t internal = 0;
-  for (uint32_t d = 0; d < 64; ++d) {
+  uint32_t d = 0;
+  for (; d < 64; ++d) {
     const uint64_t widest = ceil_div_pow2(N, d);
     const bool forced = widest > kLeafRange;
     if (!forced && widest < need) break;
@@ -89,7 +96,11 @@ uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant) {
   }
   uint64_t jobs = sat_add(sat_add(internal, internal), 1);
   if (variant == 1) jobs = sat_add(jobs, n / dcs::kFillPiece);
-  return std::min(jobs, n);
+  jobs = std::min(jobs, n);
+  const uint64_t narrowest = d >= 63 ? 0 : (N >> d);  // leaves are at depth <= d
+  if (variant == 0 && narrowest > static_cast<uint64_t>(dense_ratio) * dcs::kInlineMax)
+    jobs = std::min(jobs, n / (dcs::kInlineMax + 1));
+  return jobs;
 }
 
 // A capacity below the proven bound is used once the bound needs more than
@@ -129,7 +140,8 @@ uint64_t choose_capacity(uint64_t expected, uint64_t proven, uint64_t top_thread
 }
 
 // variant 0: without replacement, 1: with replacement.
-Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias) {
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t dense_ratio, uint32_t variant,
+               int32_t cut_bias) {
   Plan pl;
   if (n == 0) return pl;
   // Algorithm P cut: depth-`cut` subtrees hold about 2*n0 samples.
@@ -142,7 +154,16 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
   cut = std::max(cut, std::min(forced, by_count));
   const int64_t biased = static_cast<int64_t>(cut) + cut_bias;
   cut = static_cast<uint32_t>(std::max<int64_t>(0, biased));
-  cut = std::min(cut, kMaxCut);
+  // At most 2^18 threads, except where the range bound forces the tree so
+  // deep that its leaves hold at most kInlineMax values on average: there
+  // the threads' depth-first walks through the forced levels take the time,
+  // and from n = 2^23 on up to 2^20 threads (about 16 values each) shorten
+  // them by more than the splits above the cut that every extra level
+  // repeats once more.
+  const uint32_t lg = floor_log2(n);
+  const bool deep_sparse = forced > 0 && (forced >= 64 || (n >> forced) <= dcs::kInlineMax);
+  const uint32_t max_cut = deep_sparse ? std::min(kMaxCut, std::max(18u, lg > 4 ? lg - 4 : 0u)) : 18u;
+  cut = std::min(cut, max_cut);
   pl.cut = cut;
   pl.threads = 1ull << cut;
   // the top kernel computes the frontier one wave (64 threads, 6 levels)
@@ -168,7 +189,7 @@ Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cu
   uint64_t cap = 4 * ((n + n0 - 1) / n0) + 64;
   cap += std::min<uint64_t>(n, forced >= 62 ? n : (2ull << forced));
   if (variant == 1) cap += n / dcs::kFillPiece + std::min<uint64_t>(N, 4 * (n / n0) + 4) + 2;
-  pl.leaf_cap = choose_capacity(cap, leaf_bound(n, N, n0, variant), pl.top_threads,
+  pl.leaf_cap = choose_capacity(cap, leaf_bound(n, N, n0, dense_ratio, variant), pl.top_threads,
                                 &pl.second_round);
   return pl;
 }
@@ -508,7 +529,7 @@ int32_t sample_tree(uint32_t variant, uint64_t n, uint64_t N, uint64_t seed, con
   DeviceCtx* c;
   int32_t rc = device_ctx(&c);
   if (rc) return rc;
-  const Plan pl = make_plan(n, N, P.n0, variant, cut_bias_for(variant, n));
+  const Plan pl = make_plan(n, N, P.n0, P.dense_ratio, variant, cut_bias_for(variant, n));
   const TreeLayout L =
       tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads, pl.second_round);
   void* ws = workspace;
@@ -648,7 +669,8 @@ int32_t dcs_sample_part(int32_t variant, uint64_t n, uint64_t N, uint64_t seed,
   uint64_t np = std::min(n, capacity);
   if (variant == 0) np = std::min(np, range);
   np = std::max<uint64_t>(np, 1);
-  const Plan pl = make_plan(np, std::max<uint64_t>(range, 1), P.n0, static_cast<uint32_t>(variant),
+  const Plan pl = make_plan(np, std::max<uint64_t>(range, 1), P.n0, P.dense_ratio,
+                            static_cast<uint32_t>(variant),
                             cut_bias_for(static_cast<uint32_t>(variant), np));
   const TreeLayout L =
       tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads, pl.second_round);
@@ -717,7 +739,7 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
     const double m = static_cast<double>(n) *
                      (static_cast<double>(lengths[i]) / static_cast<double>(N));
     const uint64_t est = std::max<uint64_t>(1, std::min<uint64_t>(lengths[i], static_cast<uint64_t>(m)));
-    const Plan pl = make_plan(est, lengths[i], P.n0, 0, cut_bias_for(0, est));
+    const Plan pl = make_plan(est, lengths[i], P.n0, P.dense_ratio, 0, cut_bias_for(0, est));
     I.cut = pl.cut;
     I.top_cut = pl.top_cut;
     tb += pl.threads;
@@ -728,7 +750,8 @@ int32_t dcs_sample_segments(uint64_t n, const uint64_t* lengths, uint64_t K, uin
     if (forced > 0) forced_leaves += std::min<uint64_t>(n, 2ull << forced);
     ++nonempty;
     // a segment holds at most min(n, L_i) values
-    proven = sat_add(proven, leaf_bound(std::min(n, lengths[i]), lengths[i], P.n0, 0));
+    proven = sat_add(proven,
+                     leaf_bound(std::min(n, lengths[i]), lengths[i], P.n0, P.dense_ratio, 0));
   }
   bool second = false;
   const uint64_t leaf_cap = choose_capacity(
@@ -894,7 +917,7 @@ int32_t dcs_workspace_size(int32_t variant, uint64_t n, uint64_t N, double p_for
   if (variant == 0 || variant == 1) {
     if (variant == 0 && n > N) return DCS_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    const Plan pl = make_plan(n, N, P.n0, static_cast<uint32_t>(variant),
+    const Plan pl = make_plan(n, N, P.n0, P.dense_ratio, static_cast<uint32_t>(variant),
                               cut_bias_for(static_cast<uint32_t>(variant), n));
     *bytes = tree_layout(1, pl.leaf_cap, pl.threads, pl.stack_depth, pl.top_threads,
                          pl.second_round).total;
@@ -951,7 +974,8 @@ int32_t dcs_batch_create(const dcs_instance* instances, uint32_t count, dcs_batc
       delete b;
       return DCS_EINVAL;
     }
-    const Plan pl = make_plan(d.n, d.N, P.n0, d.variant, cut_bias_for(d.variant, d.n));
+    const Plan pl =
+        make_plan(d.n, d.N, P.n0, P.dense_ratio, d.variant, cut_bias_for(d.variant, d.n));
     Instance I{};
     I.n = d.n;
     I.N = d.N;
@@ -1148,7 +1172,7 @@ int32_t dcs_online_next(dcs_online* o, uint64_t first, uint64_t count, uint64_t*
   for (uint64_t i = 0; i < count; ++i) {
     const Node& r = o->roots[first + i];
     if (r.nv == 0) continue;
-    const Plan pl = make_plan(r.nv, r.Nv, o->P.n0, v, cut_bias_for(v, r.nv));
+    const Plan pl = make_plan(r.nv, r.Nv, o->P.n0, o->P.dense_ratio, v, cut_bias_for(v, r.nv));
     Instance I{};
     I.n = r.nv;
     I.N = r.Nv;
@@ -1268,12 +1292,12 @@ int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params
     return DCS_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   const uint32_t v = static_cast<uint32_t>(variant);
-  const Plan pl = make_plan(n, N, P.n0, v, cut_bias_for(v, n));
+  const Plan pl = make_plan(n, N, P.n0, P.dense_ratio, v, cut_bias_for(v, n));
   info[0] = pl.cut;
   info[1] = pl.threads;
   info[2] = pl.stack_depth;
   info[3] = pl.leaf_cap;
-  info[4] = leaf_bound(n, N, P.n0, v);
+  info[4] = leaf_bound(n, N, P.n0, P.dense_ratio, v);
   info[5] = pl.second_round ? 1 : 0;
   return DCS_OK;
 }

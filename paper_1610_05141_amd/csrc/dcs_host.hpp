@@ -35,10 +35,11 @@ struct Plan {
   // second round for tree threads whose leaves did not all fit
   bool second_round = false;
 };
-Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant, int32_t cut_bias);
-// Leaf jobs of the tree of (n, N, n0, variant) for every outcome of its
-// random splits.
-uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t variant);
+Plan make_plan(uint64_t n, uint64_t N, uint32_t n0, uint32_t dense_ratio, uint32_t variant,
+               int32_t cut_bias);
+// Leaf jobs of the tree of (n, N, n0, dense_ratio, variant) for every
+// outcome of its random splits.
+uint64_t leaf_bound(uint64_t n, uint64_t N, uint32_t n0, uint32_t dense_ratio, uint32_t variant);
 // After a call latched a capacity error: later plans take larger capacities.
 void leaf_capacity_exceeded();
 

@@ -1502,7 +1502,10 @@ __device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I)
 // the values the leaf kernels would give (the first n_v distinct non-void
 // values of the leaf's word stream mapped into [0, N_v), or with replacement
 // its first n_v non-void values with repeats, ascending), without a job.
-constexpr uint32_t kInlineMax = 4;
+// The thread keeps them sorted in its own LDS row (insertion: a repeat is
+// the value just below its place).
+constexpr uint32_t kInlineStride = kInlineMax + 1;  // rows start in distinct banks
+constexpr uint32_t kTreeBlock = 256;
 
 __device__ __forceinline__ bool leaf_inline_kind(const Node& v, const Instance& I) {
   if (v.nv > kInlineMax) return false;
@@ -1510,44 +1513,29 @@ __device__ __forceinline__ bool leaf_inline_kind(const Node& v, const Instance& 
   return static_cast<uint64_t>(I.dense_ratio) * v.nv < v.Nv;  // sparse (dense stay jobs)
 }
 
-__device__ void leaf_inline(const Node& v, const Instance& I, uint64_t* out) {
+__device__ void leaf_inline(const Node& v, const Instance& I, uint64_t* out, uint32_t* row) {
   const bool wr = I.variant == 1;
   const Stream st = make_stream(I.seed, v.id, wr ? kWrLeaf : kLeaf, 0);
   const uint32_t thr = range_threshold(v.Nv);
   const uint32_t nv = static_cast<uint32_t>(v.nv);
-  // values kept so far, in stream order; unused slots hold the largest word
-  uint32_t k0 = ~0u, k1 = ~0u, k2 = ~0u, k3 = ~0u;
   uint32_t have = 0;
   for (uint64_t blk = 0; have < nv; ++blk) {
     const uint4 w = philox_block(st, blk);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint32_t x;
-      const bool ok = range_map(pick(w, j), v.Nv, thr, &x) && have < nv;
-      const bool dup = !wr && ((have > 0 && x == k0) || (have > 1 && x == k1) ||
-                               (have > 2 && x == k2));
-      if (ok && !dup) {
-        k0 = have == 0 ? x : k0;
-        k1 = have == 1 ? x : k1;
-        k2 = have == 2 ? x : k2;
-        k3 = have == 3 ? x : k3;
-        ++have;
-      }
+      if (have >= nv || !range_map(pick(w, j), v.Nv, thr, &x)) continue;
+      uint32_t p = have;
+      while (p > 0 && row[p - 1] > x) --p;
+      if (!wr && p > 0 && row[p - 1] == x) continue;  // a repeat: not a new value
+      for (uint32_t i = have; i > p; --i) row[i] = row[i - 1];
+      row[p] = x;
+      ++have;
     }
   }
-  // ascending (five comparators sort four values)
-  uint32_t a, b;
-  a = min(k0, k1); b = max(k0, k1); k0 = a; k1 = b;
-  a = min(k2, k3); b = max(k2, k3); k2 = a; k3 = b;
-  a = min(k0, k2); b = max(k0, k2); k0 = a; k2 = b;
-  a = min(k1, k3); b = max(k1, k3); k1 = a; k3 = b;
-  a = min(k1, k2); b = max(k1, k2); k1 = a; k2 = b;
   uint64_t* o = out + I.out_offset + v.off;
   const uint64_t b1 = v.lo + 1;
-  store_out(o, b1 + k0);
-  if (nv > 1) store_out(o + 1, b1 + k1);
-  if (nv > 2) store_out(o + 2, b1 + k2);
-  if (nv > 3) store_out(o + 3, b1 + k3);
+  for (uint32_t i = 0; i < nv; ++i) store_out(o + i, b1 + row[i]);
 }
 
 // Hand leaf v over as a job (round 0: front or back list by kind; round 1:
@@ -1601,11 +1589,12 @@ __device__ __forceinline__ bool emit(const Node& v, const Instance& I, Leaf* lea
 
 // emit, and when the job array is full: in round 0 with a redo bitmap, mark
 // tree thread t for the second round; otherwise latch the capacity error.
+// row: this thread's LDS row of kInlineStride words.
 __device__ __forceinline__ bool emit_or_mark(const Node& v, const Instance& I, Leaf* leaves,
                                              uint64_t cap, Control* ctl, int round, uint32_t* redo,
-                                             uint64_t t) {
+                                             uint64_t t, uint32_t* row) {
   if (leaf_inline_kind(v, I)) {
-    leaf_inline(v, I, ctl->out);
+    leaf_inline(v, I, ctl->out, row);
     return true;
   }
   if (emit(v, I, leaves, cap, ctl, round)) return true;
@@ -1631,18 +1620,18 @@ __device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t
 // early at a leaf or an empty node (the leaf is emitted by the path whose
 // remaining bits are zero).  kWave: the 64 lanes of a wave walk one path
 // together (lane 0 emits) and share each split's rejection attempts.
-// emit_or_mark's round, redo and t apply to the leaf it may emit.
+// emit_or_mark's round, redo, t and row apply to the leaf it may emit.
 template <bool kWave = false>
 __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uint64_t g,
                                           const Instance& I, Leaf* leaves, uint64_t leaf_cap,
-                                          Control* ctl, int round = 0, uint32_t* redo = nullptr,
-                                          uint64_t t = 0) {
+                                          Control* ctl, uint32_t* row, int round = 0,
+                                          uint32_t* redo = nullptr, uint64_t t = 0) {
   for (uint32_t d = d0; d < d1; ++d) {
     if (v.nv == 0) return false;
     if (is_leaf(v, I)) {
       const uint32_t below = d1 - d;
       if ((g & ((1ull << below) - 1)) == 0 && (!kWave || (threadIdx.x & 63u) == 0))
-        emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t);
+        emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t, row);
       return false;
     }
     const uint64_t L = split_left<kWave>(v, I);
@@ -1695,12 +1684,14 @@ __device__ __forceinline__ bool part_root(Node& v, uint32_t dp, uint64_t part,
 // path first walks to the part's root (the same splits on every path),
 // the first path reports the part's count and rank, and offsets below
 // count from the part's first value.
-__global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ inst,
+__global__ __launch_bounds__(kTreeBlock) void k_tree_top(const Instance* __restrict__ inst,
                                                   uint32_t n_inst, uint64_t top_threads,
                                                   Node* frontier, Leaf* leaves, uint64_t leaf_cap,
                                                   Control* ctl, uint64_t* part_out) {
   const uint64_t t = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   if (t >= top_threads) return;  // whole waves
+  __shared__ uint32_t inl[kTreeBlock * kInlineStride];
+  uint32_t* row = inl + threadIdx.x * kInlineStride;
   const Instance I = inst[find_instance(inst, n_inst, t, true)];
   const uint64_t g = t - I.top_base;
   const bool lane0 = (threadIdx.x & 63u) == 0;
@@ -1715,21 +1706,24 @@ __global__ __launch_bounds__(256) void k_tree_top(const Instance* __restrict__ i
     v.off = 0;
     if (v.nv > I.part_cap) v.nv = 0;  // the caller's buffer is too small
     if (!inner) {
-      if (v.nv > 0 && g == 0 && lane0) emit_or_mark(v, I, leaves, leaf_cap, ctl, 0, nullptr, 0);
+      if (v.nv > 0 && g == 0 && lane0)
+        emit_or_mark(v, I, leaves, leaf_cap, ctl, 0, nullptr, 0, row);
       v.nv = 0;
     }
     d0 = I.part_depth;
   }
-  if (v.nv > 0 && !walk_path<true>(v, d0, I.top_cut, g, I, leaves, leaf_cap, ctl)) v.nv = 0;
+  if (v.nv > 0 && !walk_path<true>(v, d0, I.top_cut, g, I, leaves, leaf_cap, ctl, row)) v.nv = 0;
   if (lane0) frontier[t] = v;
 }
 
-__global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
+__global__ __launch_bounds__(kTreeBlock) void k_tree(const Instance* __restrict__ inst, uint32_t n_inst,
                                               uint64_t total_threads,
                                               const Node* __restrict__ frontier, Leaf* leaves,
                                               uint64_t leaf_cap, Node* stacks,
                                               uint32_t stack_depth, Control* ctl, uint32_t* redo,
                                               int round) {
+  __shared__ uint32_t inl[kTreeBlock * kInlineStride];
+  uint32_t* row = inl + threadIdx.x * kInlineStride;
   const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= total_threads) return;
   if (round == 1 && ((redo[t >> 5] >> (t & 31u)) & 1u) == 0) return;
@@ -1740,7 +1734,8 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
   Node v = frontier[I.top_base + (g >> rest)];
   const uint64_t gl = g & ((1ull << rest) - 1);
   // Algorithm P: the rest of the path to this thread's depth-`cut` node.
-  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, round, redo, t)) return;
+  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, row, round, redo, t))
+    return;
   // Depth-first expansion of the subtree (Algorithm R below depth `cut`).
   // Entry k of thread t's stack is stacks[k * total_threads + t], so that the
   // pushes of a wave's threads at one level share cache lines.
@@ -1750,7 +1745,7 @@ __global__ __launch_bounds__(256) void k_tree(const Instance* __restrict__ inst,
     for (;;) {
       if (v.nv == 0) break;
       if (is_leaf(v, I)) {
-        if (!emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t)) return;
+        if (!emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t, row)) return;
         break;
       }
       const uint64_t L = split_left(v, I);
@@ -2542,8 +2537,8 @@ hipError_t launch_tree_top(const Instance* inst, uint32_t n_inst, uint64_t top_t
                            Node* frontier, Leaf* leaves, uint64_t leaf_cap, Control* ctl,
                            uint64_t* part_out, hipStream_t stream) {
   if (top_threads == 0) return hipSuccess;
-  const uint64_t blocks = (top_threads * 64 + 255) / 256;  // one wave per path
-  hipLaunchKernelGGL(k_tree_top, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
+  const uint64_t blocks = (top_threads * 64 + kTreeBlock - 1) / kTreeBlock;  // one wave per path
+  hipLaunchKernelGGL(k_tree_top, dim3(static_cast<uint32_t>(blocks)), dim3(kTreeBlock), 0, stream, inst,
                      n_inst, top_threads, frontier, leaves, leaf_cap, ctl, part_out);
   return hipGetLastError();
 }
@@ -2554,8 +2549,8 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
                        hipStream_t stream) {
   if (total_threads == 0) return hipSuccess;
   if (round != 0 && redo == nullptr) return hipErrorInvalidValue;
-  const uint64_t blocks = (total_threads + 255) / 256;
-  hipLaunchKernelGGL(k_tree, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, stream, inst,
+  const uint64_t blocks = (total_threads + kTreeBlock - 1) / kTreeBlock;
+  hipLaunchKernelGGL(k_tree, dim3(static_cast<uint32_t>(blocks)), dim3(kTreeBlock), 0, stream, inst,
                      n_inst, total_threads, frontier, leaves, leaf_cap, stacks, stack_depth, ctl,
                      redo, round);
   return hipGetLastError();

@@ -111,6 +111,9 @@ constexpr int kLeafBlock = 512;             // threads of a leaf work-group
 constexpr int kBernBlock = 256;             // threads of a Bernoulli work-group
 constexpr uint32_t kMaxN0 = 4096;           // largest n0 (LDS bound of a leaf)
 constexpr uint64_t kFillPiece = 1ull << 16; // constant-fill leaves are cut to this
+// Sparse and with-replacement leaves of at most this many values are
+// sampled by the tree kernels themselves (no job record).
+constexpr uint32_t kInlineMax = 32;
 // Bernoulli chunks (both kernels) are handed out by kTicketClasses
 // counters (7: coprime to the 8 XCDs), kTicketStride words apart.
 constexpr uint32_t kTicketClasses = 7;

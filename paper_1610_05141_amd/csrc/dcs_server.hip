@@ -189,7 +189,7 @@ bool dcs_server::launch_batch() {
   for (uint64_t tk : batch) {
     const Req& R = reqs[tk];
     const uint32_t n0 = R.r.n0 ? R.r.n0 : 4096u;
-    const Plan pl = dcs::host::make_plan(R.r.n, R.r.N, n0, R.r.variant,
+    const Plan pl = dcs::host::make_plan(R.r.n, R.r.N, n0, 16u, R.r.variant,
                                          dcs::host::cut_bias_for(R.r.variant, R.r.n));
     total_n += R.r.n;
     Instance I{};

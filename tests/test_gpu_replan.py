@@ -4,18 +4,16 @@ later plans enlarged (the plan row of the hot path: "overflow is detected,
 flagged and re-planned").
 
 The capacity is forced through the library's test hook to just below the
-number of leaf jobs of the call's canonical tree, which the oracle counts
-independently (its tree for samples without replacement; a walk over its
-binomial splits here for samples with replacement).  Every output is
+number of leaf jobs of the call's canonical tree, counted from the oracle's
+splits (leaves the tree kernels do not sample themselves).  Every output is
 compared bit for bit with the oracle."""
 import numpy as np
 import pytest
 
 from tests.gpu_util import announce, dcs, first_mismatch, to_np_u64
+from tests.tree_jobs import jobs as tree_jobs
 
 pytestmark = pytest.mark.gpu
-
-FILL_PIECE = 1 << 16
 
 
 @pytest.fixture
@@ -26,28 +24,11 @@ def m():
 
 
 def wor_jobs(ref, n, N, seed, n0):
-    return ref.tree_stats(n, N, seed, n0=n0)[1]
+    return tree_jobs(ref, 0, n, N, seed, n0=n0)
 
 
 def wr_jobs(ref, n, N, seed, n0):
-    """Leaf jobs of the with-replacement tree (binomial splits; a range of one
-    element is a leaf, cut into pieces of 2^16 values)."""
-    jobs, todo = 0, [(1, N, n)]
-    while todo:
-        node, Nv, nv = todo.pop()
-        if nv == 0:
-            continue
-        if Nv == 1:
-            jobs += -(-nv // FILL_PIECE)
-            continue
-        if nv < n0 and Nv <= (1 << 32):
-            jobs += 1
-            continue
-        l = Nv // 2
-        L = ref.binom(nv, l, Nv, seed, node)
-        todo.append((2 * node, l, L))
-        todo.append((2 * node + 1, Nv - l, nv - L))
-    return jobs
+    return tree_jobs(ref, 1, n, N, seed, n0=n0)
 
 
 WOR = [
@@ -55,7 +36,7 @@ WOR = [
     # over ranges that are not; a range above 2^32
     (200_000, 1 << 40, 3, 64),
     (300_000, 5_000_000, 4, 256),
-    (60_000, (1 << 34) + 12345, 5, 32),
+    (60_000, (1 << 34) + 12345, 5, 128),
 ]
 WR = [
     (50_000, 1 << 36, 6, 128),
@@ -110,7 +91,7 @@ def test_second_round_allocation_free_and_batch(ref, m):
     want = ref.sample(n, N, seed, n0=n0)
     assert np.array_equal(to_np_u64(out), want)
 
-    insts = [(90_000, 1 << 38, 11, 64, 0), (40_000, 777_777, 12, 32, 0), (70_000, 1 << 30, 13, 64, 1)]
+    insts = [(90_000, 1 << 38, 11, 128, 0), (40_000, 777_777, 12, 32, 0), (70_000, 1 << 30, 13, 128, 1)]
     total_jobs = sum(wr_jobs(ref, a, b, c, d) if v else wor_jobs(ref, a, b, c, d)
                      for a, b, c, d, v in insts)
     per = (total_jobs - 3) // len(insts)  # the batch holds len(insts) * per slots
@@ -135,7 +116,7 @@ def test_second_round_allocation_free_and_batch(ref, m):
 def test_second_round_segments(ref, m):
     """An uneven universe: the jobs of all segments' trees share one array."""
     L = [3 << 20, 5_000_000, 1 << 33, 12345, 9 << 22]
-    n, seed, n0 = 150_000, 21, 64
+    n, seed, n0 = 150_000, 21, 128
     _, heap = ref.segment_tree(n, L, seed)
     D = max(0, (len(L) - 1).bit_length())
     counts = heap[(1 << D):(1 << D) + len(L)]

@@ -60,14 +60,19 @@ def test_small_leaf_kernel_runs(ref):
 
 
 TINY = [
-    # (variant, n, N, seed, n0): leaves of one to a few values, which the tree
-    # kernel samples itself (the range bound forces depth ~30 here)
+    # (variant, n, N, seed, n0): leaves of one to 32 values, which the tree
+    # kernel samples itself (the range bound forces the tree deep, or n0 is
+    # small)
     (0, 300_000, 1 << 60, 31, None),
     (0, 200_000, (1 << 58) + 12345, 32, None),   # ranges that are not powers of two
     (1, 250_000, (1 << 55) + 7, 33, None),
     (0, 60_000, 1 << 40, 34, 3),                  # n0 = 3: leaves of 1 or 2 values
     (1, 80_000, 1 << 20, 35, 4),                  # with replacement: repeats inside tiny leaves
     (0, 5_000, 1 << 16, 36, 2),                   # leaves of one value; dense ones stay jobs
+    (0, 1 << 20, 1 << 40, 37, 32),                # leaves of 16..31 values
+    (1, 300_000, 1 << 36, 38, 20),                # with replacement, up to 19 values
+    (0, 1 << 24, 1 << 54, 40, None),              # ~4 values per leaf, tails past 10
+    (0, 400_000, 3_000_000_019, 41, 33),          # up to 32 values, ranges not powers of two
 ]
 
 
@@ -78,7 +83,7 @@ def test_tiny_leaves_bitexact(ref, case):
     kw = {} if n0 is None else {"n0": n0}
     if variant == 0:
         _, leaves, _ = ref.tree_stats(n, N, seed, **kw)
-        assert n / leaves <= 4, (leaves, n / leaves)
+        assert n / leaves <= 32, (leaves, n / leaves)
     announce(f"tiny leaves case {case}: variant={variant} n={n} N={N} seed={seed} n0={n0}")
     f = m.sample if variant == 0 else m.sample_replacement
     out = f(n, N, seed, **kw)

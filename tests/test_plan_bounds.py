@@ -1,5 +1,7 @@
 """The tree plan's bounds (host logic, no GPU): the proven bound on leaf jobs
 and the depth-first stack bound hold for every outcome of the random splits.
+Jobs are the leaves the tree kernels do not sample themselves (sparse and
+with-replacement leaves of at most 32 values they do).
 
 Tiny universes: exhaustive worst case over every value a split can take
 (the hypergeometric / binomial supports), computed here from the tree's
@@ -13,12 +15,10 @@ import pytest
 
 import oracle
 import paper_1610_05141_amd as dcs
-
-LEAF_RANGE = 1 << 32
-FILL_PIECE = 1 << 16
+from tests.tree_jobs import FILL_PIECE, INLINE_MAX, LEAF_RANGE, jobs as tree_jobs
 
 
-def worst_case(variant: int, N: int, n: int, n0: int):
+def worst_case(variant: int, N: int, n: int, n0: int, dense_ratio: int = 16):
     """(most leaf jobs, deepest internal node) over all split outcomes."""
 
     @lru_cache(maxsize=None)
@@ -28,7 +28,11 @@ def worst_case(variant: int, N: int, n: int, n0: int):
         if variant == 1 and Nv == 1:
             return -(-nv // FILL_PIECE), -1
         if nv < n0 and Nv <= LEAF_RANGE:
-            return 1, -1
+            if variant == 1:
+                inline = nv <= INLINE_MAX
+            else:
+                inline = nv <= INLINE_MAX and dense_ratio * nv < Nv
+            return (0 if inline else 1), -1
         l = Nv // 2
         lo = 0 if variant == 1 else max(0, nv - (Nv - l))
         hi = nv if variant == 1 else min(nv, l)
@@ -68,7 +72,7 @@ def test_bounds_hold_where_the_level_count_binds(variant):
     internal nodes per level (2I + 1 < n), not from n, in most cases."""
     binding = 0
     for N in (64, 100, 255, 256):
-        for n0 in (8, 16):
+        for n0 in (8, 16, 40):
             for n in range(1, 65):
                 if variant == 0 and n > N:
                     continue
@@ -87,20 +91,33 @@ def test_bound_reached_by_adversarial_outcome():
     assert jobs <= p["leaf_bound"] <= 2 * jobs + 1
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_bounds_hold_with_leaves_of_either_kind(variant):
+    """n0 = 40 (leaves of up to 39 values, some sampled by the tree kernels,
+    some jobs, dense ones among them on the narrow ranges): every outcome."""
+    for N in (1 << 12, 5000, 1 << 14):
+        for n in range(40, 200, 7):
+            jobs, _ = worst_case(variant, N, n, 40)
+            p = dcs.debug_plan(variant, n, N, n0=40)
+            assert p["leaf_bound"] >= jobs, (variant, n, N, p, jobs)
+
+
 @pytest.mark.parametrize("n,N,n0", [
     (1 << 16, 1 << 40, 64), (5000, (1 << 34) + 123, 16), (1 << 14, 1 << 52, 256),
     (300, (1 << 45) + 7, 4), (1 << 18, (1 << 33) - 5, 4096), (1 << 20, 1 << 24, 512),
 ])
 def test_bounds_hold_on_oracle_trees(n, N, n0):
-    """Trees of the canonical definition (the oracle's, 12 seeds each),
+    """Trees of the canonical definition (the oracle's splits, 4 seeds each),
     including range-forced levels above 2^32: jobs within the bound (and the
     capacity, without the second round), depth within the stack bound."""
     p = dcs.debug_plan(0, n, N, n0=n0)
-    for seed in range(12):
+    for seed in range(4):
         internal, leaves, depth_max = oracle.tree_stats(n, N, seed, n0=n0)
-        assert leaves <= p["leaf_bound"], (seed, leaves, p)
+        jobs = tree_jobs(oracle, 0, n, N, seed, n0=n0)
+        assert jobs <= leaves
+        assert jobs <= p["leaf_bound"], (seed, jobs, p)
         if not p["second_round"]:
-            assert leaves <= p["leaf_cap"]
+            assert jobs <= p["leaf_cap"]
         # internal nodes sit above the deepest node; a thread's stack holds at
         # most one entry per level between the cut and the last internal level
         assert depth_max - p["cut"] <= p["stack_depth"], (seed, depth_max, p)
@@ -119,5 +136,8 @@ def test_plan_choice():
     assert wr["leaf_bound"] >= wr["leaf_cap"] and wr["second_round"]
     for n, N in [(1, 1), (7, 7), (1 << 10, 1 << 62), (123456, 1 << 33)]:
         p = dcs.debug_plan(0, n, N, n0=2)
-        assert 1 <= p["leaf_bound"] <= n
+        assert p["leaf_bound"] <= n
         assert p["leaf_cap"] >= p["threads"] // 64 + 1
+    # sparse over a huge universe: jobs only for leaves of 33 or more values
+    g = dcs.debug_plan(0, 1 << 24, (1 << 30) * ((1 << 30) - 1) // 2)
+    assert g["leaf_cap"] <= (1 << 24) // 33 + 1 and not g["second_round"]
