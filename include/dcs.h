@@ -135,15 +135,11 @@ int32_t dcs_sample_replacement_ex(uint64_t n, uint64_t N, uint64_t seed,
  * *count_dev with capacity after synchronizing; re-running with a larger
  * buffer gives the identical sample.
  * Concurrency: the chunks' output offsets come from a decoupled look-back in
- * which a chunk waits for its predecessors' counts.  Chunks are handed out
- * by seven counters (chunk j by counter j mod 7, in order within each), so
- * progress needs a running work-group of every class; the launch sizes its
- * grid so that every class has one when the kernel has the GPU to itself.
- * Do not run a Bernoulli call (or G(n, p)) concurrently with other long
- * kernels on another stream: if the other kernel keeps a class from running,
- * waves poll up to 2^26 times (seconds), then the call latches an error
- * (DCS_EDEVICE at dcs_synchronize) and the sample is lost.  Calls on one
- * stream, or concurrent with short kernels only, are unaffected.
+ * which a chunk waits for its predecessors' counts.  A wave that has polled
+ * a silent predecessor 4096 times (its chunk may not have a running wave,
+ * for instance while another kernel on another stream holds the GPU)
+ * computes that chunk's hit count itself, a function of the chunk alone,
+ * and goes on; so a call completes whatever runs beside it.
  */
 int32_t dcs_sample_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t* out_dev,
                              uint64_t capacity, uint64_t* count_dev, void* stream);
@@ -454,6 +450,11 @@ int32_t dcs_tune_reset(void);
  * to 1.  DCS_EINVAL if capacity >= 2^31.
  */
 int32_t dcs_debug_leaf_capacity(uint64_t capacity, int32_t reset_boost, uint32_t* boost);
+/* dcs_debug_lookback_help -- test hook: a Bernoulli look-back (dcs_sample_
+ * bernoulli, G(n, p)) counts a silent predecessor chunk itself after `polls`
+ * polls instead of 4096 (0 restores the default; 1 makes the waiting waves
+ * count nearly every predecessor they wait for).  Never changes a sample. */
+int32_t dcs_debug_lookback_help(uint32_t polls);
 /* dcs_debug_plan -- the plan of a tree call (host only, no device work):
  * info[0] cut depth, [1] tree threads, [2] DFS stack entries per thread,
  * [3] leaf-job capacity, [4] the proven bound on leaf jobs, [5] 1 if the

@@ -18,6 +18,7 @@ __all__ = [
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Online", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "debug_plan", "debug_leaf_capacity",
+    "debug_lookback_help",
     "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
@@ -40,7 +41,7 @@ EXPORTED_SYMBOLS = (
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
     "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset", "dcs_debug_leaf_capacity",
-    "dcs_debug_plan", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
+    "dcs_debug_plan", "dcs_debug_lookback_help", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
     "dcs_online_destroy",
 )
 
@@ -134,6 +135,7 @@ def lib() -> ctypes.CDLL:
             "dcs_tune_reset": (i32, []),
             "dcs_debug_leaf_capacity": (i32, [u64, i32, ctypes.POINTER(u32)]),
             "dcs_debug_plan": (i32, [i32, u64, u64, pp, ctypes.POINTER(u64)]),
+            "dcs_debug_lookback_help": (i32, [u32]),
             "dcs_online_create": (i32, [i32, u64, u64, u64, pp, u32, vp, ctypes.POINTER(vp)]),
             "dcs_online_counts": (i32, [vp, u64, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
             "dcs_online_next": (i32, [vp, u64, u64, vp, u64, ctypes.POINTER(u64), vp]),
@@ -458,6 +460,12 @@ def debug_plan(variant: int, n: int, N: int, n0: int = 0, dense_ratio: int = 0) 
     return {"cut": int(info[0]), "threads": int(info[1]), "stack_depth": int(info[2]),
             "leaf_cap": int(info[3]), "leaf_bound": int(info[4]),
             "second_round": bool(info[5])}
+
+
+def debug_lookback_help(polls: int) -> None:
+    """Test hook: Bernoulli look-backs count a silent predecessor chunk
+    themselves after `polls` polls (0: the default)."""
+    _check(lib().dcs_debug_lookback_help(int(polls)), "dcs_debug_lookback_help")
 
 
 def debug_leaf_capacity(capacity: int, reset_boost: bool = False) -> int:

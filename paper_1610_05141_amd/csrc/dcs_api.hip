@@ -112,6 +112,9 @@ constexpr uint64_t kProvenJobs = 1ull << 20;
 // call latched a capacity error.
 std::atomic<uint64_t> g_debug_leaf_cap{0};
 std::atomic<uint32_t> g_cap_boost{1};
+// Test hook (dcs_debug_lookback_help): polls before a Bernoulli look-back
+// counts a silent predecessor itself, 0 = the default.
+std::atomic<uint32_t> g_debug_help_polls{0};
 
 void leaf_capacity_exceeded() {
   uint32_t b = g_cap_boost.load();
@@ -896,8 +899,10 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
   const uint32_t grid = static_cast<uint32_t>(
       std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * occ)));
   timing_begin(3, s, &t1);
+  const uint32_t help = g_debug_help_polls.load();
   e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,
-                            count_dev, ctl, tickets, grid, lds_cap, s);
+                            count_dev, ctl, tickets, grid, lds_cap,
+                            help != 0 ? help : dcs::kHelpPolls, s);
   timing_end(s, &t1);
   if (e != hipSuccess) return DCS_EHIP;
   return DCS_OK;
@@ -1299,6 +1304,11 @@ int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params
   info[3] = pl.leaf_cap;
   info[4] = leaf_bound(n, N, P.n0, P.dense_ratio, v);
   info[5] = pl.second_round ? 1 : 0;
+  return DCS_OK;
+}
+
+int32_t dcs_debug_lookback_help(uint32_t polls) {
+  g_debug_help_polls.store(polls);
   return DCS_OK;
 }
 

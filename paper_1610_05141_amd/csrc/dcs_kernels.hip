@@ -1924,6 +1924,40 @@ __device__ uint64_t bern_pass(const Stream& st, uint64_t len, double c64, uint32
   return count;
 }
 
+// The hit count of a double-precision chunk (bern_pass's draws: 64-bit draw
+// 2b + j is word pair j of Philox block b; hit k while the running position
+// stays within len), counted by one wave, 128 draws per step.  The positions
+// are exact integers, so this count equals bern_pass's whatever the grouping.
+__device__ uint64_t bern_count64_wave(const Stream& st, uint64_t len, double c64, uint32_t lane) {
+  uint64_t last = 0, count = 0;
+  for (uint32_t blk0 = 0;; blk0 += 64) {
+    const uint4 w = philox_block(st, blk0 + lane);
+    const uint64_t d0 = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
+    const uint64_t d1 = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
+    uint64_t inc[2];
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      const double g = floor(log64(unit_open0(j ? d1 : d0)) * c64);
+      const double gc = g < 0x1p33 ? g : 0x1p33;
+      inc[j] = static_cast<uint64_t>(gc) + 1;
+    }
+    const uint64_t sum = inc[0] + inc[1];
+    const uint64_t incl = wave_scan_incl(sum);
+    const uint64_t total = __shfl(incl, 63, 64);
+    const uint64_t q1 = last + incl - sum + inc[0];
+    const uint64_t q2 = q1 + inc[1];
+    const uint32_t in = (q1 <= len ? 1u : 0u) + (q2 <= len ? 1u : 0u);
+    if (last + total <= len) {
+      count += 128;
+      last += total;
+      continue;
+    }
+    const unsigned long long whole = __ballot(in == 2u);
+    const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+    return count + 2ull * nw + (nw < 64 ? static_cast<uint32_t>(__shfl(in, nw, 64)) : 0u);
+  }
+}
+
 // Decoupled look-back (one wave): chunk j's exclusive prefix is the sum of the
 // aggregates of its predecessors back to the nearest one that has published an
 // inclusive prefix.  Each step reads 64 predecessors at once.  Returns the
@@ -1931,8 +1965,15 @@ __device__ uint64_t bern_pass(const Stream& st, uint64_t len, double c64, uint32
 // A status word carries its whole message (flag and value in one 64-bit
 // atomic), so relaxed agent-scope atomics suffice; release/acquire would add
 // a write-back and an invalidation of the whole L2 per access.
+// A predecessor that has published nothing after help_polls polls (its wave
+// may not be running: another kernel can hold the GPU) has its hit count
+// computed by this wave instead, count_of(i), a function of the chunk alone
+// (Sec. 4.7: chunks are independent); the count is offered to other waves
+// (compare-and-swap, only over an empty word) and the look-back goes on, so
+// it ends whatever runs beside it.  From then on the wave helps at once.
+template <class CountOf>
 __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64_t cnt,
-                                  Control* ctl) {
+                                  Control* ctl, uint32_t help_polls, CountOf count_of) {
   const uint32_t lane = threadIdx.x & 63;
   if (j == 0) {
     if (lane == 0)
@@ -1944,19 +1985,41 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
   uint64_t acc = 0;
   long long top = static_cast<long long>(j) - 1;
   uint32_t spins = 0;
+  bool helping = false;
+  // this lane's predecessor counted by this wave (valid while `helped` is
+  // set, for the current window of 64)
+  bool helped = false;
+  uint64_t own = 0;
   for (;;) {
     const long long i = top - static_cast<long long>(lane);
     // Positions before chunk 0 read as an inclusive prefix of 0.
-    const unsigned long long s =
+    unsigned long long s =
         i >= 0 ? __hip_atomic_load(&status[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                : kFlagIncl;
+    if (helped && (s & ~kValueMask) == 0) s = kFlagAgg | own;
     const unsigned long long flag = s & ~kValueMask;
     const unsigned long long incl = __ballot(flag == kFlagIncl);
     const unsigned long long none = __ballot(flag == 0);
     const uint32_t first = incl ? static_cast<uint32_t>(__builtin_ctzll(incl)) : 64u;
     const unsigned long long upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
     if (none & upto) {
-      if (++spins > kSpinLimit) {
+      if (helping || ++spins > help_polls) {
+        helping = true;
+        // the nearest predecessor without a word
+        const uint32_t h = static_cast<uint32_t>(__builtin_ctzll(none & upto));
+        const uint64_t ih = static_cast<uint64_t>(top) - h;
+        const uint64_t c = count_of(ih);
+        if (lane == h) {
+          helped = true;
+          own = c;
+          unsigned long long expect = 0;
+          __hip_atomic_compare_exchange_strong(&status[ih], &expect, kFlagAgg | c,
+                                               __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        continue;
+      }
+      if (spins > kSpinLimit) {  // unreachable while help_polls < kSpinLimit
         if (lane == 0) atomicOr(ctl->err, kErrSpinLimit);
         break;
       }
@@ -1969,6 +2032,7 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
     acc += v;
     if (first < 64) break;
     top -= 64;
+    helped = false;
   }
   if (lane == 0)
     __hip_atomic_store(&status[j], kFlagIncl | (acc + cnt), __ATOMIC_RELAXED,
@@ -1979,15 +2043,15 @@ __device__ uint64_t bern_lookback(unsigned long long* status, uint64_t j, uint64
 // Chunks are handed out as in k_bern_wave: n_cls counters kTicketStride
 // words apart, work-group class c = blockIdx mod n_cls taking chunks c,
 // c + n_cls, ... in order (one shared counter serializes the hand-out at
-// about one chunk per same-address atomic; every class has a resident
-// work-group, so the look-back always progresses).
+// about one chunk per same-address atomic); a chunk held up is counted by
+// the waiting look-back itself.
 __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, uint64_t chunk,
                                                      uint64_t n_chunks, double c64,
                                                      unsigned long long* status, uint64_t* out,
                                                      uint64_t capacity, uint64_t* count_dev,
                                                      Control* ctl, uint32_t lds_cap,
                                                      unsigned long long* tickets,
-                                                     uint32_t n_cls) {
+                                                     uint32_t n_cls, uint32_t help_polls) {
   extern __shared__ uint32_t pos[];  // lds_cap offsets (dynamic)
   __shared__ uint64_t scr64[8];
   __shared__ uint32_t ends;
@@ -2006,7 +2070,11 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
     const uint64_t cnt =
         bern_pass(st, len, c64, pos, lds_cap, false, out, 0, capacity, base, scr64, &ends);
     if (threadIdx.x < 64) {
-      const uint64_t acc = bern_lookback(status, j, cnt, ctl);
+      const uint64_t acc = bern_lookback(status, j, cnt, ctl, help_polls, [&](uint64_t i) {
+        const uint64_t bi = i * chunk;
+        return bern_count64_wave(make_stream(seed, i, kBChunk, 0),
+                                 (N - bi) < chunk ? (N - bi) : chunk, c64, threadIdx.x & 63u);
+      });
       if (threadIdx.x == 0) {
         excl = acc;
         if (j == n_chunks - 1) {
@@ -2059,12 +2127,35 @@ __device__ __forceinline__ void put_incs(uint16_t* dst, const uint32_t inc[4]) {
   *reinterpret_cast<uint2*>(dst) = v;
 }
 
+// The hit count of a single-precision chunk, counted by one wave exactly as
+// k_bern_wave counts its own chunk (without keeping the positions).
+__device__ uint32_t bern_count32_wave(const Stream& st, uint32_t len, float c32, uint32_t lane) {
+  uint32_t q_base = 0, cnt = 0;
+  for (uint32_t c = 0;; ++c) {
+    uint32_t inc[4];
+    const uint32_t sum = bern_group(st, c, lane, c32, inc);
+    const uint32_t incl = wave_scan_incl(sum);
+    uint32_t r = incl - sum, in = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r += inc[k];
+      in += q_base + r <= len ? 1u : 0u;
+    }
+    const unsigned long long whole = __ballot(in == 4u);
+    const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+    const uint32_t got = nw == 64u ? kBernWaveGroup : 4u * nw + __builtin_amdgcn_readlane(in, nw);
+    cnt += got;
+    q_base += __builtin_amdgcn_readlane(incl, 63);
+    if (got < kBernWaveGroup) return cnt;
+  }
+}
+
 __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uint64_t chunk,
                                                   uint64_t n_chunks, float c32,
                                                   unsigned long long* status, uint64_t* out,
                                                   uint64_t capacity, uint64_t* count_dev,
                                                   Control* ctl, unsigned long long* tickets,
-                                                  uint32_t n_cls) {
+                                                  uint32_t n_cls, uint32_t help_polls) {
   __shared__ __align__(16) uint16_t list[kBernWaveList];
   __shared__ uint32_t gbase[kBernWaveGroups + 1];  // position before group c (c <= 15)
   const uint32_t lane = lane_tid();
@@ -2073,9 +2164,9 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
   // class c = blockIdx mod n_cls takes chunks c, c + n_cls, ... in order.
   // Same-address atomics serialize, so one shared counter would cap the
   // chunk rate; with n_cls coprime to the 8 XCDs that work-groups alternate
-  // over, any n_cls work-groups on one XCD cover every class, so a chunk not
-  // yet handed out always has a running wave that will take it (which the
-  // look-back's progress needs).
+  // over, any n_cls work-groups on one XCD cover every class.  When a chunk
+  // is held up anyway (its class has no running wave because another kernel
+  // holds the GPU), the look-back counts it itself (bern_lookback).
   const uint32_t cls = blockIdx.x % n_cls;
   unsigned long long* const ticket = tickets + cls * kTicketStride;
   for (;;) {
@@ -2115,7 +2206,12 @@ __global__ __launch_bounds__(64) void k_bern_wave(uint64_t N, uint64_t seed, uin
       q_base += adv;
       if (got < kBernWaveGroup) break;
     }
-    const uint64_t first = bern_lookback(status, j, cnt, ctl);
+    const uint64_t first = bern_lookback(status, j, cnt, ctl, help_polls, [&](uint64_t i) {
+      const uint64_t bi = i * chunk;
+      return static_cast<uint64_t>(bern_count32_wave(
+          make_stream(seed, i, kBChunk, 0),
+          static_cast<uint32_t>((N - bi) < chunk ? (N - bi) : chunk), c32, lane));
+    });
     if (lane == 0 && j == n_chunks - 1) {
       *count_dev = first + cnt;
       ctl->bern_count = first + cnt;
@@ -2592,17 +2688,17 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             int fp32, double c64, float c32, unsigned long long* status,
                             uint64_t* out, uint64_t capacity, uint64_t* count_dev, Control* ctl,
                             unsigned long long* tickets, uint32_t grid, uint32_t lds_cap,
-                            hipStream_t stream) {
+                            uint32_t help_polls, hipStream_t stream) {
   (void)p;
   const uint32_t n_cls = grid < kTicketClasses ? grid : kTicketClasses;
   if (fp32)
     hipLaunchKernelGGL(k_bern_wave, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
-                       status, out, capacity, count_dev, ctl, tickets, n_cls);
+                       status, out, capacity, count_dev, ctl, tickets, n_cls, help_polls);
   else
     hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock),
                        static_cast<size_t>(lds_cap) * sizeof(uint32_t), stream, N, seed, chunk,
                        n_chunks, c64, status, out, capacity, count_dev, ctl, lds_cap, tickets,
-                       n_cls);
+                       n_cls, help_polls);
   return hipGetLastError();
 }
 

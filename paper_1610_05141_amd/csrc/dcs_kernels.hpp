@@ -183,7 +183,11 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,
                             uint64_t* count_dev, Control* ctl, unsigned long long* tickets,
-                            uint32_t grid, uint32_t lds_cap, hipStream_t stream);
+                            uint32_t grid, uint32_t lds_cap, uint32_t help_polls,
+                            hipStream_t stream);
+// Polls of a Bernoulli look-back on a chunk that has published nothing
+// before the waiting wave counts that chunk itself.
+constexpr uint32_t kHelpPolls = 4096;
 // Online sampling: the 2^depth part roots of instance I's depth-`depth` cut
 // (node with off = the part's rank; an empty part has nv = 0, a leaf above
 // the cut goes whole to the leftmost part below it).
