@@ -243,7 +243,7 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
             f = dcs.sample if kind == "wor" else dcs.sample_replacement
             run = lambda: f(n, N, seed, out=out, stream=stream)
             kernels = {"k_leaf_pow2": 4, "k_leaf_mixed": 5, "k_leaf_dense": 6,
-                       "k_leaf_small": 12}
+                       "k_leaf_small": 12, "k_leaf_once": 13}
         run()
         dcs.synchronize(stream)
         dcs.profile_enable(True)
@@ -604,6 +604,7 @@ def main() -> int:
     mixed_ms, mixed_n = dcs.profile_read(5)   # work-group leaf kernel of the other kinds
     dense_ms, dense_n = dcs.profile_read(6)   # one-wave dense leaf kernel
     small_ms, small_n = dcs.profile_read(12)  # one-wave small leaf kernel
+    once_ms, once_n = dcs.profile_read(13)    # one-pass kernel of repeating sparse leaves
     tree_ms, tree_n = dcs.profile_read(1)
     reset_ms, reset_n = dcs.profile_read(0)
     dcs.profile_enable(False)
@@ -651,6 +652,7 @@ def main() -> int:
                                 "k_leaf_mixed": mixed_ms / max(mixed_n, 1),
                                 "k_leaf_dense": dense_ms / max(dense_n, 1),
                                 "k_leaf_small": small_ms / max(small_n, 1),
+                                "k_leaf_once": once_ms / max(once_n, 1),
                                 "leaf_stage": stage_ms / max(stage_n, 1)},
         "whole_step_write_GBs": BYTES_PER_SAMPLE * N_SAMPLE / (ms_per_step * 1e-3) / 1e9,
         "invariants_ok": props_ok,

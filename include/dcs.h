@@ -480,7 +480,10 @@ const char* dcs_status_string(int32_t status);
  * dcs_sample_segments, 9 / 10 / 11 = the count passes / the scan and
  * repair / the write passes of dcs_sample_wholerange, 12 = one-wave-per-leaf
  * kernel of the sparse and with-replacement jobs of at most 1024 values over
- * ranges that are not powers of two); DCS_EINVAL for another kind. */
+ * ranges that are not powers of two (and of the sparse ones over powers of
+ * two that are expected to repeat), 13 = work-group kernel of the sparse jobs
+ * of more than 1024 values with n_v^2 >= 2 N_v, which samples each in one
+ * pass instead of repeat rounds); DCS_EINVAL for another kind. */
 int32_t dcs_profile_enable(int32_t enable);
 int32_t dcs_profile_read(int32_t kind, double* total_ms, uint64_t* launches);
 /* Restrict the timing to the kinds whose bit is set in `mask` (bit k: kind

@@ -490,8 +490,10 @@ def profile_read(kind: int):
     stage (all leaf kernels), 3 Bernoulli, 4 leaf kernel of the sparse and
     with-replacement jobs over power-of-two ranges, 5 work-group leaf kernel
     of the other jobs, 6 one-wave dense leaf kernel, 7 edge decoding, 8
-    segment splits, 9 / 10 / 11 whole-range B count / repair / write,
-    accumulated since profile_enable (read after synchronize)."""
+    segment splits, 9 / 10 / 11 whole-range B count / repair / write, 12
+    one-wave leaf kernel of jobs of at most 1024 values, 13 one-pass kernel
+    of sparse jobs expected to repeat, accumulated since profile_enable (read
+    after synchronize)."""
     ms = ctypes.c_double(0)
     n = ctypes.c_uint64(0)
     _check(lib().dcs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dcs_profile_read")

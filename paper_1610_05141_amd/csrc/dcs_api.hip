@@ -319,7 +319,7 @@ void release_timings() {
 // of the segments of an uneven universe, 9 / 10 / 11 whole-range
 // Algorithm B: count passes / scan and repair / write passes, 12 one-wave
 // leaf kernel of the small sparse and with-replacement leaves
-constexpr int kProfKinds = 13;
+constexpr int kProfKinds = 14;
 double g_prof_ms[kProfKinds] = {};
 uint64_t g_prof_n[kProfKinds] = {};
 
@@ -476,12 +476,21 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   Timing t4{}, t5{};
   timing_begin(2, s, &t2);
   timing_begin(4, s, &t4);
-  e = dcs::launch_leaf(true, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+  e = dcs::launch_leaf(dcs::kLeafFront, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want),
+                       s);
   timing_end(s, &t4);
   if (e == hipSuccess) {
     timing_begin(5, s, &t5);
-    e = dcs::launch_leaf(false, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+    e = dcs::launch_leaf(dcs::kLeafBack, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want),
+                         s);
     timing_end(s, &t5);
+  }
+  Timing t13{};
+  if (e == hipSuccess) {
+    timing_begin(13, s, &t13);
+    e = dcs::launch_leaf(dcs::kLeafOnce, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want),
+                         s);
+    timing_end(s, &t13);
   }
   Timing t6{};
   if (e == hipSuccess) {

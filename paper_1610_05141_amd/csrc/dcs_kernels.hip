@@ -683,6 +683,196 @@ __device__ uint32_t first_round_regs(const Stream& st, uint32_t nv, const RangeI
   return total0 + (total >> 16);
 }
 
+// A sparse leaf whose first n_v values are expected to repeat (n_v^2 / (2 N_v)
+// of at least one; see once_by_group): one pass over the first W words
+// instead of repeat rounds.  W covers n_v plus margins for void words and for repeats
+// (at most 4096).  Every non-void value among them is counted into its bucket
+// and ranked inside the bucket by (value, word index); a value whose bucket
+// holds the same value at a smaller word index repeats an earlier one.  The
+// words that are first occurrences, in stream order, give the first n_v
+// distinct values (Algorithm H's set); their bucket ranks are their sorted
+// positions among all W words, and a scan over the positions of the kept
+// ones compacts them.  When fewer than n_v distinct values occur among the W
+// words, those values are sorted and the repeat rounds continue from word W.
+// Returns where the sorted sample lies (sm.tmp, or sm.keys after rounds).
+template <int B>
+__device__ const uint32_t* leaf_sparse_once(const Stream& st, uint32_t nv, const RangeInfo& ri,
+                                 uint32_t shift, uint32_t nb, LeafSmem& sm) {
+  constexpr int kBlk = kKeys / (4 * B);
+  constexpr int kQ = 4 * kBlk;
+  constexpr int kPer = kBuckets / B;
+  static_assert(kBlk == 2, "two 16-bit counts share one scanned word");
+  static_assert(kPer * B == kKeys && kPer == 8, "one byte of the position bitmap per thread");
+  const uint32_t tid = lane_tid();
+  uint32_t* cnt = sm.buck;
+  uint32_t* keys = sm.keys;
+  uint16_t* widx = reinterpret_cast<uint16_t*>(sm.tmp);  // word index by bucket position
+  zero_counters<B>(cnt, tid);
+  // W: n_v, the expected repeats r with a margin, and twice the expected void
+  // words plus 32
+  const uint64_t r = (static_cast<uint64_t>(nv) * nv) / (2 * ri.s);
+  const uint64_t base = nv + r + (r >> 2) + 4 * isqrt64(r) + 16;
+  const uint64_t full = base + ((2 * base * ri.thr) >> 32) + 32;
+  const uint32_t W = full < kKeys ? static_cast<uint32_t>(full) : kKeys;
+  const uint32_t nblk = (W + 3) >> 2;
+  uint32_t key[kQ];
+  uint32_t ok = 0;
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t blk = tid + k * B;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) key[4 * k + j] = 0;
+    if (blk < nblk) {
+      const uint4 w = philox_block(st, blk);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint32_t v;
+        const bool good = range_map(pick(w, j), ri.s, ri.thr, &v);
+        key[4 * k + j] = v;
+        if (good && 4 * blk + j < W) ok |= 1u << (4 * k + j);
+      }
+    }
+  }
+  __syncthreads();
+  // 1. count into buckets; each key keeps its counter index | slot << 16
+  uint32_t as[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    as[q] = 0;
+    if ((ok >> q) & 1u) {
+      const uint32_t a = bpad(key[q] >> shift);
+      as[q] = a | (atomicAdd(&cnt[a], 1u) << 16);
+    }
+  }
+  __syncthreads();
+  // 2. exclusive scan of the counts; the word after the last bucket holds the
+  // total, the end of the last bucket
+  {
+    uint32_t* run8 = cnt + bpad(kPer * tid);
+    uint32_t c[kPer];
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      c[k] = run8[k];
+      run += c[k];
+    }
+    uint32_t total;
+    uint32_t acc = block_scan_excl<B, uint32_t, false>(run, sm.scr, &total);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      run8[k] = acc;
+      acc += c[k];
+    }
+    if (tid == 0) cnt[kSpareCount] = total;
+  }
+  __syncthreads();
+  // 3. scatter values and word indices in bucket order; each key keeps its
+  // bucket's start | count << 13 | min(slot, 4) << 26
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * k + j;
+      if ((ok >> q) & 1u) {
+        const uint32_t a = as[q] & 0xFFFFu;
+        const uint32_t b = key[q] >> shift;
+        const uint32_t s0 = cnt[a], e0 = cnt[bpad(b + 1)];
+        const uint32_t slot = as[q] >> 16;
+        const uint32_t p = s0 + slot;
+        keys[p] = key[q];
+        widx[p] = static_cast<uint16_t>(4 * (tid + k * B) + j);
+        as[q] = s0 | ((e0 - s0) << 13) | (min(slot, 4u) << 26);
+      }
+    }
+  }
+  __syncthreads();
+  // the counters are dead from here on: region B's first words become the
+  // bitmap of kept sorted positions (cleared before the scan's barrier below)
+  uint32_t* kept_bits = cnt;
+  if (tid < kKeys / 32) kept_bits[tid] = 0;
+  // 4. rank inside the bucket by (value, word index); each key's register
+  // then holds its sorted position among the W words.  A bucket's first four
+  // entries are read at once (the words past a bucket's end lie inside region
+  // A and are ignored); larger buckets continue one entry at a time.
+  uint32_t rep = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    if ((ok >> q) & 1u) {
+      const uint32_t s0 = as[q] & 0x1FFFu, c = (as[q] >> 13) & 0x1FFFu, self = as[q] >> 26;
+      const uint32_t t = 4 * (tid + (q >> 2) * B) + (q & 3);
+      uint32_t rk = 0, eq = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t v = keys[s0 + u];
+        const bool in = static_cast<uint32_t>(u) < c;
+        rk += (in && v < key[q]) ? 1u : 0u;
+        eq |= (in && v == key[q]) ? (1u << u) : 0u;
+      }
+      for (uint32_t i = s0 + 4; i < s0 + c; ++i) {
+        const uint32_t v = keys[i];
+        rk += v < key[q] ? 1u : 0u;
+        if (v == key[q] && widx[i] < t) {
+          ++rk;
+          rep |= 1u << q;
+        }
+      }
+      eq &= ~(1u << self);  // self < 4: its own entry; self = 4: none of the four
+      if (eq != 0) {        // the value occurs again among the first four
+        for (uint32_t m = eq; m != 0; m &= m - 1u) {
+          const uint32_t i = s0 + static_cast<uint32_t>(__ffs(m) - 1);
+          if (widx[i] < t) {
+            ++rk;
+            rep |= 1u << q;
+          }
+        }
+      }
+      as[q] = s0 + rk;
+    }
+  }
+  // 5. first occurrences in stream order: the first n_v of them are kept
+  const uint32_t first = ok & ~rep;
+  uint32_t total;
+  const uint32_t packed = static_cast<uint32_t>(__popc(first & 0xFu)) |
+                          (static_cast<uint32_t>(__popc(first >> 4)) << 16);
+  const uint32_t excl = block_scan_excl<B, uint32_t>(packed, sm.scr, &total);
+  const uint32_t total0 = total & 0xFFFFu;
+  const uint32_t distinct = total0 + (total >> 16);
+  const uint32_t take = distinct < nv ? distinct : nv;
+  // 6. kept values to their sorted positions (every read of the bucket-order
+  // arrays is behind the scan's barriers)
+#pragma unroll
+  for (int k = 0; k < kBlk; ++k) {
+    const uint32_t b0 = k == 0 ? (excl & 0xFFFFu) : total0 + (excl >> 16);
+    const uint32_t fk = (first >> (4 * k)) & 0xFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * k + j;
+      const uint32_t sr = b0 + static_cast<uint32_t>(__popc(fk & ((1u << j) - 1u)));
+      if (((fk >> j) & 1u) && sr < take) {
+        const uint32_t p = as[q];
+        keys[p] = key[q];
+        atomicOr(&kept_bits[p >> 5], 1u << (p & 31u));
+      }
+    }
+  }
+  __syncthreads();
+  // 7. compact the kept positions in order into sm.tmp
+  const uint32_t byte = (kept_bits[tid >> 2] >> (8 * (tid & 3u))) & 0xFFu;
+  uint32_t unused;
+  uint32_t o = block_scan_excl<B, uint32_t>(static_cast<uint32_t>(__popc(byte)), sm.scr, &unused);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if ((byte >> j) & 1u) sm.tmp[o++] = keys[8 * tid + j];
+  __syncthreads();
+  if (take == nv) return sm.tmp;
+  // fewer than n_v distinct values among the W words: they are the rounds'
+  // starting set, and the rounds continue from word W
+  for (uint32_t i = tid; i < take; i += B) keys[i] = sm.tmp[i];
+  __syncthreads();
+  sparse_rounds<B>(st, W, take, nv, ri, shift, nb, sm);
+  return keys;
+}
+
 template <int B>
 __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   const uint32_t nv = L.nv;
@@ -707,6 +897,23 @@ __device__ void leaf_sparse(const Leaf& L, uint64_t* out, LeafSmem& sm) {
   }
   __builtin_amdgcn_s_setprio(0);
   write_sorted_pairs<B>(out + L.off, L.lo, sm.keys, nv);
+}
+
+// Sparse leaves of more than kSmallMax values whose first n_v values are
+// expected to repeat (n_v^2 >= 2 N_v, any range) run in k_leaf_once, in one
+// pass; k_leaf_mixed skips them, so that its own leaf bodies keep their
+// registers.
+template <int B>
+__device__ void leaf_once(const Leaf& L, uint64_t* out, LeafSmem& sm) {
+  const uint32_t nv = L.nv;
+  const RangeInfo ri = range_info(L.Nv);
+  uint32_t shift, nb;
+  bucket_params(L.Nv, nv, &shift, &nb);
+  const Stream st = make_stream(L.seed, L.id, kLeaf, 0);
+  __builtin_amdgcn_s_setprio(2);  // the passes ahead of other work-groups
+  const uint32_t* sorted = leaf_sparse_once<B>(st, nv, ri, shift, nb, sm);
+  __builtin_amdgcn_s_setprio(0);
+  write_sorted_pairs<B>(out + L.off, L.lo, sorted, nv);
 }
 
 // Sparse or with-replacement leaf on a power-of-two range (no word is void):
@@ -1099,6 +1306,14 @@ __device__ __forceinline__ bool small_by_wave(const Leaf& L) {
   return (kind == kKindSparse || kind == kKindWr) && L.nv <= kSmallMax;
 }
 
+// Back-list jobs of k_leaf_once (both rounds): sparse leaves of more than
+// kSmallMax values with n_v^2 >= 2 N_v, i.e. at least one repeat expected
+// among their first n_v values.
+__device__ __forceinline__ bool once_by_group(const Leaf& L) {
+  return (L.flags & 3u) == kKindSparse && L.nv > kSmallMax &&
+         static_cast<uint64_t>(L.nv) * L.nv >= 2 * L.Nv;
+}
+
 // The first `need` non-void values in [0, s) of the 32-bit stream from word
 // t0 on, in stream order, into dst[0..need), by one wave: lane l maps the
 // words of Philox block (t >> 2) + l, a wave scan ranks the non-void ones.
@@ -1305,15 +1520,19 @@ __device__ __forceinline__ uint64_t job_counts(const Control* ctl, int round) {
 
 // Persistent leaf loop: job i of the class's list goes to work-group
 // i mod G, whose job records are read kCacheLeaves at a time into LDS.
-// kPow2: the front list (sparse and with-replacement leaves over power-of-two
-// ranges) with only that leaf body compiled in, so that the hot path keeps
-// its values in registers; otherwise the back list with every other leaf
-// body, leaving to the one-wave kernels the jobs they take.  round2: the
-// second round's jobs (back list only, every kind, none left to the one-wave
-// kernels).
-template <int B, bool kPow2>
+// kListFront: the front list (sparse and with-replacement leaves over
+// power-of-two ranges, except sparse ones expected to repeat) with only that
+// leaf body compiled in, so that the hot path keeps its values in registers.
+// kListBack: the back list with every other leaf body, leaving to the
+// one-wave kernels and to k_leaf_once the jobs they take; round2: the second
+// round's jobs (back list only, every kind, none left to the one-wave
+// kernels).  kListOnce: the back list's jobs of once_by_group, both rounds.
+constexpr int kListFront = 0, kListBack = 1, kListOnce = 2;
+
+template <int B, int kList>
 __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
                                           uint64_t* out, Control* ctl, int round2 = 0) {
+  constexpr bool kPow2 = kList == kListFront;
   __shared__ uint32_t smem[kSmemWords];
   LeafSmem sm;
   sm.keys = smem;
@@ -1328,7 +1547,8 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
   if (front + back > leaf_cap) {
     // cannot happen (granted slots sum to at most the capacity): report it
     // and sample nothing
-    if (!kPow2 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(ctl->err, kErrLeafCapacity);
+    if (kList == kListBack && blockIdx.x == 0 && threadIdx.x == 0)
+      atomicOr(ctl->err, kErrLeafCapacity);
     return;
   }
   const uint64_t n_leaves = kPow2 ? front : back;
@@ -1368,20 +1588,23 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
             c.Nv = static_cast<uint64_t>(r[4]) | (static_cast<uint64_t>(r[5]) << 32);
             c.nv = r[10];
             c.flags = r[11];
-            run = round2 || (!dense_by_wave(c) && !small_by_wave(c));
+            if (kList == kListOnce)
+              run = once_by_group(c);
+            else
+              run = !once_by_group(c) && (round2 || (!dense_by_wave(c) && !small_by_wave(c)));
           }
           const unsigned long long m = __ballot(run);
           if (tid == 0) sm.scr[kScrKeep] = static_cast<uint32_t>(m);
         }
         __syncthreads();
         keep = __builtin_amdgcn_readfirstlane(sm.scr[kScrKeep]);
-        if (keep == 0) {  // the whole group is the one-wave kernels'
+        if (keep == 0) {  // the whole group is other kernels'
           j += kCacheLeaves - 1;
           continue;
         }
       }
     }
-    if (!kPow2 && !((keep >> slot) & 1u)) continue;  // a one-wave kernel's
+    if (!kPow2 && !((keep >> slot) & 1u)) continue;  // another kernel's
     Leaf L;
     {
       const uint4* c = reinterpret_cast<const uint4*>(cache + slot * kLeafWords);
@@ -1409,6 +1632,9 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
       // pass still reads, and its sentinels and flag wait for the counting
       // barrier, which every thread reaches only after its output pass.
       leaf_sparse_pow2<B>(L, out, sm);
+    } else if constexpr (kList == kListOnce) {
+      leaf_once<B>(L, out, sm);
+      __syncthreads();
     } else {
       switch (L.flags & 3u) {
         case kKindSparse: leaf_sparse<B>(L, out, sm); break;
@@ -1424,13 +1650,19 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
 template <int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_pow2(
     const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl) {
-  leaf_loop<B, true>(leaves, leaf_cap, out, ctl);
+  leaf_loop<B, kListFront>(leaves, leaf_cap, out, ctl);
 }
 
 template <int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_mixed(
     const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl, int round2) {
-  leaf_loop<B, false>(leaves, leaf_cap, out, ctl, round2);
+  leaf_loop<B, kListBack>(leaves, leaf_cap, out, ctl, round2);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_once(
+    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl, int round2) {
+  leaf_loop<B, kListOnce>(leaves, leaf_cap, out, ctl, round2);
 }
 
 // Dense leaves of the back list, one wave (and work-group) per leaf: back job
@@ -1552,14 +1784,34 @@ __device__ __forceinline__ bool emit(const Node& v, const Instance& I, Leaf* lea
   if (kind == kKindFill && v.nv > kFillPiece) pieces = (v.nv + kFillPiece - 1) / kFillPiece;
   // sparse and with-replacement leaves over a power-of-two range fill the
   // job array from the front, everything else from the back; the leaf
-  // kernel of the other class reports the two lists meeting
-  const bool front =
-      round == 0 && (kind == kKindSparse || kind == kKindWr) && (v.Nv & (v.Nv - 1)) == 0;
-  // one counter word at a uniform address, so that the compiler combines
-  // the wave's increments into a single atomic
-  const unsigned long long old =
-      atomicAdd(round == 0 ? &ctl->leaf_counts : &ctl->leaf_counts2,
-                front ? 1ull : static_cast<unsigned long long>(pieces) << 32);
+  // kernel of the other class reports the two lists meeting.  Sparse leaves
+  // whose values are expected to repeat (n_v^2 >= 2 N_v) go to the back,
+  // where the one-pass sampler finds the repeats.
+  const bool front = round == 0 && (v.Nv & (v.Nv - 1)) == 0 &&
+                     (kind == kKindWr || (kind == kKindSparse && v.nv * v.nv < 2 * v.Nv));
+  // One counter word (front jobs in its low half, back jobs in its high
+  // half) and one atomic per wave for the jobs of one slot each: the lanes
+  // take the counter values a sequence of single increments in lane order
+  // would have returned.  Constant leaves cut into several pieces take an
+  // atomic of their own.
+  unsigned long long* counter = round == 0 ? &ctl->leaf_counts : &ctl->leaf_counts2;
+  const bool single = pieces == 1;
+  const unsigned long long mf = __ballot(single && front);
+  const unsigned long long mb = __ballot(single && !front);
+  unsigned long long old = 0;
+  if ((mf | mb) != 0) {
+    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(mf | mb)) - 1);
+    unsigned long long at0 = 0;
+    if ((threadIdx.x & 63u) == leader)
+      at0 = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mf)) +
+                                   (static_cast<unsigned long long>(__popcll(mb)) << 32));
+    at0 = static_cast<unsigned long long>(
+              __builtin_amdgcn_readlane(static_cast<uint32_t>(at0), leader)) |
+          (static_cast<unsigned long long>(
+               __builtin_amdgcn_readlane(static_cast<uint32_t>(at0 >> 32), leader)) << 32);
+    old = at0 + lane_rank(mf) + (static_cast<unsigned long long>(lane_rank(mb)) << 32);
+  }
+  if (!single) old = atomicAdd(counter, static_cast<unsigned long long>(pieces) << 32);
   const uint64_t asked = (old & 0xFFFFFFFFull) + (old >> 32);  // slots before this job
   if (asked + pieces > cap) {
     // the one job that crosses the capacity records the granted counts
@@ -2652,20 +2904,29 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
+hipError_t launch_leaf(int which, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream) {
-  if (pow2_list)
+  if (which == kLeafFront)
     hipLaunchKernelGGL(k_leaf_pow2<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                        leaf_cap, out, ctl);
-  else
+  else if (which == kLeafBack)
     hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                        leaf_cap, out, ctl, 0);
+  else if (which == kLeafOnce)
+    hipLaunchKernelGGL(k_leaf_once<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
+                       leaf_cap, out, ctl, 0);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
                               uint32_t grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
+                     leaf_cap, out, ctl, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_leaf_once<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                      leaf_cap, out, ctl, 1);
   return hipGetLastError();
 }

@@ -162,13 +162,17 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
                        const Node* frontier, Leaf* leaves, uint64_t leaf_cap, Node* stacks,
                        uint32_t stack_depth, Control* ctl, uint32_t* redo, int round,
                        hipStream_t stream);
-// Leaf kernel over one of the two job lists: pow2_list = the front list
-// (sparse and with-replacement leaves over power-of-two ranges), else the
-// back list's jobs that the one-wave kernels do not take.
-hipError_t launch_leaf(bool pow2_list, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
+// Work-group leaf kernels: kLeafFront = the front list (sparse and
+// with-replacement leaves over power-of-two ranges, except sparse ones
+// expected to repeat); kLeafBack = the back list's jobs that no other kernel
+// takes; kLeafOnce = the back list's sparse leaves of more than 1024 values
+// with n_v^2 >= 2 N_v (one-pass sampler).
+constexpr int kLeafFront = 0, kLeafBack = 1, kLeafOnce = 2;
+hipError_t launch_leaf(int which, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
                        Control* ctl, uint32_t grid, hipStream_t stream);
 // The second round's jobs (all on the back list, every kind run by the
-// work-group bodies); returns at once when round 0 handed over every leaf.
+// work-group kernels of the back list); returns at once when round 0 handed
+// over every leaf.
 hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
                               uint32_t grid, hipStream_t stream);
 // Dense leaves of the back list whose range fits 16-bit positions, one wave
