@@ -92,6 +92,7 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, unsigned j) {
 struct Draws64 {
   Stream s;
   uint64_t t;
+  uint32_t gbits = 6;  // wave mode: groups of 2^gbits lanes share a deviate
   __device__ __forceinline__ uint64_t next() {
     const uint4 b = philox_block(s, static_cast<uint32_t>(t >> 1));
     const uint64_t v = (t & 1) ? (static_cast<uint64_t>(b.z) | (static_cast<uint64_t>(b.w) << 32))
@@ -304,25 +305,37 @@ __device__ __forceinline__ bool rou_accept(double u, double T, bool* reject) {
 
 // The ratio-of-uniforms loop: attempt a takes draws 2a (U) and 2a+1 (V),
 // i.e. Philox block a, and the deviate is the first accepted attempt.
-// kWave: the 64 lanes of a wave, all sampling the same deviate, try
-// attempts 64r + lane of round r and take the lowest accepted one (the same
-// deviate, found in one round instead of one attempt after another).
+// kWave: the lanes of a wave form aligned groups of G = 2^d.gbits lanes
+// (the whole wave when gbits = 6), each group sampling one deviate; lane r
+// of a group tries attempt G*j + r in round j, and the group takes its
+// lowest accepted attempt (the same deviate, found in one round instead of
+// one attempt after another).
 template <bool kWave, class Attempt>
 __device__ __forceinline__ uint64_t rou_first_accepted(Draws64& d, Attempt attempt) {
   if constexpr (kWave) {
     uint32_t lane = threadIdx.x & 63u;
     asm volatile("" : "+v"(lane));
+    const uint32_t size = 1u << d.gbits;
+    const uint32_t r = lane & (size - 1u);
+    const uint32_t base = lane - r;
+    const unsigned long long gmask = d.gbits >= 6 ? ~0ull : (1ull << size) - 1ull;
     for (uint32_t round = 0;; ++round) {
-      const uint4 b = philox_block(d.s, round * 64u + lane);
+      const uint4 b = philox_block(d.s, round * size + r);
       const double u = unit_open0(static_cast<uint64_t>(b.x) | (static_cast<uint64_t>(b.y) << 32));
       const double v = unit_closed0(static_cast<uint64_t>(b.z) | (static_cast<uint64_t>(b.w) << 32));
       uint64_t k = 0;
       const bool ok = attempt(u, v, &k);
-      const unsigned long long m = __ballot(ok);
+      const unsigned long long m = (__ballot(ok) >> base) & gmask;
       if (m != 0) {
         const uint32_t f = static_cast<uint32_t>(__ffsll(static_cast<long long>(m)) - 1);
-        const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(k), f);
-        const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(k >> 32), f);
+        uint32_t lo, hi;
+        if (d.gbits >= 6) {
+          lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(k), f);
+          hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(k >> 32), f);
+        } else {
+          lo = static_cast<uint32_t>(__shfl(static_cast<int>(k), static_cast<int>(base + f)));
+          hi = static_cast<uint32_t>(__shfl(static_cast<int>(k >> 32), static_cast<int>(base + f)));
+        }
         return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
       }
     }
@@ -386,15 +399,16 @@ __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N,
 
 // Hyp(n, M, N): successes among n draws without replacement from N items, M
 // of them successes; stream (seed, node, purpose, 0), purpose SPLIT for the
-// recursion tree.  kWave: called by all 64 lanes of a wave with the same
-// arguments.
+// recursion tree.  kWave: called by every lane of the wave, each aligned
+// group of 2^gbits lanes with the same arguments.
 template <bool kWave = false>
 __device__ __forceinline__ uint64_t hypergeometric(uint64_t n, uint64_t M, uint64_t N, uint64_t seed,
-                                   uint64_t node, uint32_t purpose = kSplit) {
+                                   uint64_t node, uint32_t purpose = kSplit,
+                                   uint32_t gbits = 6) {
   if (n == 0 || M == 0) return 0;
   if (M == N) return n;
   if (n == N) return M;
-  Draws64 d{make_stream(seed, node, purpose, 0), 0};
+  Draws64 d{make_stream(seed, node, purpose, 0), 0, gbits};
   const bool flip_n = n > N - n;
   const uint64_t n1 = flip_n ? N - n : n;
   const bool flip_m = M > N - M;
@@ -452,13 +466,15 @@ __device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t 
   });
 }
 
-// Bin(n, l/Nv) from stream (seed, node, WRSPLIT, 0).  kWave: called by all
-// 64 lanes of a wave with the same arguments.
+// Bin(n, l/Nv) from stream (seed, node, WRSPLIT, 0).  kWave: called by
+// every lane of the wave, each aligned group of 2^gbits lanes with the same
+// arguments.
 template <bool kWave = false>
-__device__ __forceinline__ uint64_t binomial(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed, uint64_t node) {
+__device__ __forceinline__ uint64_t binomial(uint64_t n, uint64_t l, uint64_t Nv, uint64_t seed,
+                                             uint64_t node, uint32_t gbits = 6) {
   if (n == 0 || l == 0) return 0;
   if (l == Nv) return n;
-  Draws64 d{make_stream(seed, node, kWrSplit, 0), 0};
+  Draws64 d{make_stream(seed, node, kWrSplit, 0), 0, gbits};
   if (l > Nv - l) return n - binom_core<kWave>(n, Nv - l, Nv, d);
   return binom_core<kWave>(n, l, Nv, d);
 }

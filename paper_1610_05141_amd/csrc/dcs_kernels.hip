@@ -1722,11 +1722,13 @@ __device__ __forceinline__ bool is_leaf(const Node& v, const Instance& I) {
   return v.nv < I.n0 && v.Nv <= kLeafMaxRange;
 }
 
+// kWave: aligned groups of 2^gbits lanes split the same node together.
 template <bool kWave = false>
-__device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I) {
+__device__ __forceinline__ uint64_t split_left(const Node& v, const Instance& I,
+                                               uint32_t gbits = 6) {
   const uint64_t l = v.Nv >> 1;
-  return I.variant == 1 ? binomial<kWave>(v.nv, l, v.Nv, I.seed, v.id)
-                        : hypergeometric<kWave>(v.nv, l, v.Nv, I.seed, v.id);
+  return I.variant == 1 ? binomial<kWave>(v.nv, l, v.Nv, I.seed, v.id, gbits)
+                        : hypergeometric<kWave>(v.nv, l, v.Nv, I.seed, v.id, kSplit, gbits);
 }
 
 // Leaves of at most kInlineMax values, sparse or with replacement, are
@@ -1872,8 +1874,12 @@ __device__ __forceinline__ uint32_t find_instance(const Instance* inst, uint32_t
 // early at a leaf or an empty node (the leaf is emitted by the path whose
 // remaining bits are zero).  kWave: the 64 lanes of a wave walk one path
 // together (lane 0 emits) and share each split's rejection attempts.
-// emit_or_mark's round, redo, t and row apply to the leaf it may emit.
-template <bool kWave = false>
+// kGroups (d1 - d0 = 6, lane l walking g with low bits l from one shared
+// node): at depth d the lanes whose paths agree above bit d1-1-d hold the
+// same node, an aligned group of 2^(d1-d) lanes that share its split's
+// rejection attempts.  emit_or_mark's round, redo, t and row apply to the
+// leaf it may emit.
+template <bool kWave = false, bool kGroups = false>
 __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uint64_t g,
                                           const Instance& I, Leaf* leaves, uint64_t leaf_cap,
                                           Control* ctl, uint32_t* row, int round = 0,
@@ -1886,7 +1892,7 @@ __device__ __forceinline__ bool walk_path(Node& v, uint32_t d0, uint32_t d1, uin
         emit_or_mark(v, I, leaves, leaf_cap, ctl, round, redo, t, row);
       return false;
     }
-    const uint64_t L = split_left<kWave>(v, I);
+    const uint64_t L = kGroups ? split_left<true>(v, I, d1 - d) : split_left<kWave>(v, I);
     const uint64_t l = v.Nv >> 1;
     if ((g >> (d1 - 1 - d)) & 1) {
       v = Node{2 * v.id + 1, v.lo + l, v.Nv - l, v.nv - L, v.off + L};
@@ -1986,7 +1992,15 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree(const Instance* __restrict_
   Node v = frontier[I.top_base + (g >> rest)];
   const uint64_t gl = g & ((1ull << rest) - 1);
   // Algorithm P: the rest of the path to this thread's depth-`cut` node.
-  if (v.nv == 0 || !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, row, round, redo, t))
+  // When the wave's 64 lanes are the 64 paths below one frontier node, the
+  // lanes on a common node share its split's rejection attempts.
+  const bool grouped =
+      __ballot(rest == 6 && gl == (threadIdx.x & 63u) &&
+               ii == __builtin_amdgcn_readfirstlane(ii)) == ~0ull;
+  if (v.nv == 0) return;
+  if (grouped ? !walk_path<false, true>(v, 0, rest, gl, I, leaves, leaf_cap, ctl, row, round,
+                                        redo, t)
+              : !walk_path(v, 0, rest, gl, I, leaves, leaf_cap, ctl, row, round, redo, t))
     return;
   // Depth-first expansion of the subtree (Algorithm R below depth `cut`).
   // Entry k of thread t's stack is stacks[k * total_threads + t], so that the
