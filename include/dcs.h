@@ -455,6 +455,13 @@ int32_t dcs_debug_leaf_capacity(uint64_t capacity, int32_t reset_boost, uint32_t
  * polls instead of 4096 (0 restores the default; 1 makes the waiting waves
  * count nearly every predecessor they wait for).  Never changes a sample. */
 int32_t dcs_debug_lookback_help(uint32_t polls);
+/* dcs_debug_bernoulli_list -- test hook: double-precision Bernoulli chunks
+ * (p < 2^-10, and G(n, p)) keep `words` hit positions in LDS instead of the
+ * size derived from the chunk's expected hits, so that chunks with more hits
+ * write the rest in their second pass; 1 to 1024 words select the one-wave
+ * kernel, more the work-group kernel (0 restores the default).  Never changes
+ * a sample.  DCS_EINVAL above 8256 words. */
+int32_t dcs_debug_bernoulli_list(uint32_t words);
 /* dcs_debug_plan -- the plan of a tree call (host only, no device work):
  * info[0] cut depth, [1] tree threads, [2] DFS stack entries per thread,
  * [3] leaf-job capacity, [4] the proven bound on leaf jobs, [5] 1 if the

@@ -18,7 +18,7 @@ __all__ = [
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Online", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "debug_plan", "debug_leaf_capacity",
-    "debug_lookback_help",
+    "debug_lookback_help", "debug_bernoulli_list",
     "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
@@ -41,7 +41,7 @@ EXPORTED_SYMBOLS = (
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
     "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset", "dcs_debug_leaf_capacity",
-    "dcs_debug_plan", "dcs_debug_lookback_help", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
+    "dcs_debug_plan", "dcs_debug_lookback_help", "dcs_debug_bernoulli_list", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
     "dcs_online_destroy",
 )
 
@@ -136,6 +136,7 @@ def lib() -> ctypes.CDLL:
             "dcs_debug_leaf_capacity": (i32, [u64, i32, ctypes.POINTER(u32)]),
             "dcs_debug_plan": (i32, [i32, u64, u64, pp, ctypes.POINTER(u64)]),
             "dcs_debug_lookback_help": (i32, [u32]),
+            "dcs_debug_bernoulli_list": (i32, [u32]),
             "dcs_online_create": (i32, [i32, u64, u64, u64, pp, u32, vp, ctypes.POINTER(vp)]),
             "dcs_online_counts": (i32, [vp, u64, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
             "dcs_online_next": (i32, [vp, u64, u64, vp, u64, ctypes.POINTER(u64), vp]),
@@ -466,6 +467,13 @@ def debug_lookback_help(polls: int) -> None:
     """Test hook: Bernoulli look-backs count a silent predecessor chunk
     themselves after `polls` polls (0: the default)."""
     _check(lib().dcs_debug_lookback_help(int(polls)), "dcs_debug_lookback_help")
+
+
+def debug_bernoulli_list(words: int) -> None:
+    """Test hook: double-precision Bernoulli chunks keep `words` hit
+    positions in LDS (1-1024: the one-wave kernel, more: the work-group
+    kernel; 0: the default size)."""
+    _check(lib().dcs_debug_bernoulli_list(int(words)), "dcs_debug_bernoulli_list")
 
 
 def debug_leaf_capacity(capacity: int, reset_boost: bool = False) -> int:

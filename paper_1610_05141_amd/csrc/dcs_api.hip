@@ -115,6 +115,9 @@ std::atomic<uint32_t> g_cap_boost{1};
 // Test hook (dcs_debug_lookback_help): polls before a Bernoulli look-back
 // counts a silent predecessor itself, 0 = the default.
 std::atomic<uint32_t> g_debug_help_polls{0};
+// Test hook (dcs_debug_bernoulli_list): LDS positions per double-precision
+// chunk (0: from the chunk's expected hits).
+std::atomic<uint32_t> g_debug_bern_list{0};
 
 void leaf_capacity_exceeded() {
   uint32_t b = g_cap_boost.load();
@@ -903,13 +906,21 @@ int32_t dcs_sample_bernoulli_ex(double p, uint64_t N, uint64_t seed, const dcs_p
     if (want < static_cast<double>(lds_cap))
       lds_cap = (static_cast<uint32_t>(want) + 63u) & ~63u;
   }
-  const uint64_t occ =
-      static_cast<uint64_t>(fp32 ? c->bern_wave_occupancy : dcs::bern_occupancy(lds_cap));
+  const uint32_t forced_list = g_debug_bern_list.load();
+  if (!fp32 && forced_list != 0) lds_cap = forced_list;
+  // chunks expecting few hits (a short LDS list) take one wave each
+  const int kind = fp32 ? dcs::kBernFp32Wave
+                        : (lds_cap <= dcs::kBern64WaveMaxList ? dcs::kBernFp64Wave
+                                                              : dcs::kBernFp64Group);
+  const uint64_t occ = static_cast<uint64_t>(
+      kind == dcs::kBernFp32Wave   ? c->bern_wave_occupancy
+      : kind == dcs::kBernFp64Wave ? dcs::bern64_wave_occupancy(lds_cap)
+                                   : dcs::bern_occupancy(lds_cap));
   const uint32_t grid = static_cast<uint32_t>(
       std::max<uint64_t>(1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * occ)));
   timing_begin(3, s, &t1);
   const uint32_t help = g_debug_help_polls.load();
-  e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, fp32, c64, c32, status, out_dev, capacity,
+  e = dcs::launch_bernoulli(p, N, seed, chunk, n_chunks, kind, c64, c32, status, out_dev, capacity,
                             count_dev, ctl, tickets, grid, lds_cap,
                             help != 0 ? help : dcs::kHelpPolls, s);
   timing_end(s, &t1);
@@ -1318,6 +1329,12 @@ int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params
 
 int32_t dcs_debug_lookback_help(uint32_t polls) {
   g_debug_help_polls.store(polls);
+  return DCS_OK;
+}
+
+int32_t dcs_debug_bernoulli_list(uint32_t words) {
+  if (words > 2 * dcs::kMaxN0 + 64) return DCS_EINVAL;
+  g_debug_bern_list.store(words);
   return DCS_OK;
 }
 

@@ -2360,6 +2360,97 @@ __global__ __launch_bounds__(kBernBlock) void k_bern(uint64_t N, uint64_t seed, 
   }
 }
 
+// One wave's pass over a double-precision chunk: the draws and positions of
+// bern_pass (64-bit draws 2b and 2b+1 of Philox block b; lane l takes block
+// 64r + l in round r, so the positions grow with lane and draw).  First pass
+// (out == nullptr): positions - 1 of hits below lds_cap go to pos[] and the
+// hit count is returned; second pass: the hits from lds_cap on are written
+// to out[first + k] as base + position.
+__device__ uint64_t bern64_pass(const Stream& st, uint64_t len, double c64, uint32_t lane,
+                                uint32_t* pos, uint32_t lds_cap, uint64_t* out, uint64_t first,
+                                uint64_t capacity, uint64_t base) {
+  uint64_t last = 0, count = 0;
+  for (uint32_t blk0 = 0;; blk0 += 64) {
+    const uint4 w = philox_block(st, blk0 + lane);
+    const uint64_t d0 = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
+    const uint64_t d1 = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
+    uint64_t inc[2];
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      const double g = floor(log64(unit_open0(j ? d1 : d0)) * c64);
+      const double gc = g < 0x1p33 ? g : 0x1p33;
+      inc[j] = static_cast<uint64_t>(gc) + 1;
+    }
+    const uint64_t sum = inc[0] + inc[1];
+    const uint64_t incl = wave_scan_incl(sum);
+    const uint64_t total = uniform64(__shfl(incl, 63, 64));
+    const uint64_t q[2] = {last + incl - sum + inc[0], last + incl};
+    const uint64_t idx0 = count + 2ull * lane;
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      if (q[j] <= len) {
+        const uint64_t idx = idx0 + j;
+        if (out == nullptr) {
+          if (idx < lds_cap) pos[idx] = static_cast<uint32_t>(q[j] - 1);
+        } else if (idx >= lds_cap && first + idx < capacity) {
+          store_out(out + first + idx, base + q[j]);
+        }
+      }
+    }
+    if (last + total <= len) {
+      count += 128;
+      last += total;
+      continue;
+    }
+    // hits are a prefix of the round's draws (positions increase)
+    const uint32_t in = (q[0] <= len ? 1u : 0u) + (q[1] <= len ? 1u : 0u);
+    const unsigned long long whole = __ballot(in == 2u);
+    const uint32_t nw = static_cast<uint32_t>(__popcll(whole));
+    return count + 2ull * nw + (nw < 64 ? static_cast<uint32_t>(__shfl(in, nw, 64)) : 0u);
+  }
+}
+
+// Double-precision Bernoulli chunks that expect few hits (chunks clamped at
+// 2^32 for small p), one wave per chunk and no barrier: the hits of k_bern's
+// definition, the first lds_cap positions kept in LDS while the look-back
+// runs, the rest recomputed when written; consecutive lanes write
+// consecutive outputs.
+__global__ __launch_bounds__(64) void k_bern64_wave(uint64_t N, uint64_t seed, uint64_t chunk,
+                                                    uint64_t n_chunks, double c64,
+                                                    unsigned long long* status, uint64_t* out,
+                                                    uint64_t capacity, uint64_t* count_dev,
+                                                    Control* ctl, uint32_t lds_cap,
+                                                    unsigned long long* tickets, uint32_t n_cls,
+                                                    uint32_t help_polls) {
+  extern __shared__ uint32_t pos[];  // lds_cap positions - 1 (dynamic)
+  const uint32_t lane = lane_tid();
+  const uint32_t cls = blockIdx.x % n_cls;
+  unsigned long long* const ticket = tickets + cls * kTicketStride;
+  for (;;) {
+    uint64_t jt = 0;
+    if (lane == 0) jt = atomicAdd(ticket, 1ull);
+    const uint64_t j = cls + uniform64(jt) * n_cls;
+    if (j >= n_chunks) break;
+    const uint64_t base = j * chunk;
+    const uint64_t len = (N - base) < chunk ? (N - base) : chunk;
+    const Stream st = make_stream(seed, j, kBChunk, 0);
+    const uint64_t cnt = bern64_pass(st, len, c64, lane, pos, lds_cap, nullptr, 0, 0, 0);
+    const uint64_t first = bern_lookback(status, j, cnt, ctl, help_polls, [&](uint64_t i) {
+      const uint64_t bi = i * chunk;
+      return bern_count64_wave(make_stream(seed, i, kBChunk, 0),
+                               (N - bi) < chunk ? (N - bi) : chunk, c64, lane);
+    });
+    if (lane == 0 && j == n_chunks - 1) {
+      *count_dev = first + cnt;
+      ctl->bern_count = first + cnt;
+    }
+    const uint64_t held = cnt < lds_cap ? cnt : lds_cap;
+    for (uint64_t i = lane; i < held; i += 64)
+      if (first + i < capacity) store_out(out + first + i, base + static_cast<uint64_t>(pos[i]) + 1);
+    if (cnt > lds_cap) bern64_pass(st, len, c64, lane, pos, lds_cap, out, first, capacity, base);
+  }
+}
+
 // Single-precision Bernoulli chunks (p >= 2^-10), one wave per chunk and no
 // barrier: chunk j's hits are its draws up to the one that passes the chunk
 // end (Sec. 4.7's skips).  The wave keeps each 256-draw group of the first
@@ -2885,6 +2976,16 @@ int bern_wave_occupancy() {
   return occ;
 }
 
+int bern64_wave_occupancy(uint32_t lds_cap) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, reinterpret_cast<const void*>(k_bern64_wave), 64,
+          static_cast<size_t>(lds_cap) * sizeof(uint32_t)) != hipSuccess ||
+      occ <= 0)
+    occ = 1;
+  return occ;
+}
+
 int bern_occupancy(uint32_t lds_cap) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -2966,9 +3067,14 @@ hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint32_t help_polls, hipStream_t stream) {
   (void)p;
   const uint32_t n_cls = grid < kTicketClasses ? grid : kTicketClasses;
-  if (fp32)
+  if (fp32 == kBernFp32Wave)
     hipLaunchKernelGGL(k_bern_wave, dim3(grid), dim3(64), 0, stream, N, seed, chunk, n_chunks, c32,
                        status, out, capacity, count_dev, ctl, tickets, n_cls, help_polls);
+  else if (fp32 == kBernFp64Wave)
+    hipLaunchKernelGGL(k_bern64_wave, dim3(grid), dim3(64),
+                       static_cast<size_t>(lds_cap) * sizeof(uint32_t), stream, N, seed, chunk,
+                       n_chunks, c64, status, out, capacity, count_dev, ctl, lds_cap, tickets,
+                       n_cls, help_polls);
   else
     hipLaunchKernelGGL(k_bern, dim3(grid), dim3(kBernBlock),
                        static_cast<size_t>(lds_cap) * sizeof(uint32_t), stream, N, seed, chunk,

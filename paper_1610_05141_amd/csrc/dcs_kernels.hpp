@@ -143,6 +143,7 @@ int small_occupancy();
 // kernel holding lds_cap offsets in LDS, and of the one-wave
 // single-precision one.
 int bern_occupancy(uint32_t lds_cap);
+int bern64_wave_occupancy(uint32_t lds_cap);
 int bern_wave_occupancy();
 // Top of the tree: 2^top_cut threads per instance walk to the depth-top_cut
 // frontier (written to `frontier`, one slot per top thread).
@@ -183,6 +184,14 @@ hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* ou
 // values, one wave per leaf (k_leaf_mixed skips them).
 hipError_t launch_leaf_small(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
                              uint32_t grid, hipStream_t stream);
+// Bernoulli chunk kernels: kBernFp64Group = k_bern (double-precision skips,
+// one work-group per chunk), kBernFp32Wave = k_bern_wave (p >= 2^-10),
+// kBernFp64Wave = k_bern64_wave (double precision, one wave per chunk, for
+// chunks whose expected hits fit a small LDS list).
+constexpr int kBernFp64Group = 0, kBernFp32Wave = 1, kBernFp64Wave = 2;
+// Largest LDS position list (32-bit words) for which the one-wave
+// double-precision kernel is chosen.
+constexpr uint32_t kBern64WaveMaxList = 1024;
 hipError_t launch_bernoulli(double p, uint64_t N, uint64_t seed, uint64_t chunk,
                             uint64_t n_chunks, int fp32, double c64, float c32,
                             unsigned long long* status, uint64_t* out, uint64_t capacity,

@@ -18,6 +18,7 @@ CASES = [
     (0.5, 1 << 22, 43, 2),         # chunks of 2^12, most written in two passes
     (2.0**-11, 1 << 30, 44, None), # double precision
     (2.0**-20, 1 << 44, 45, None), # double precision, chunks clamped at 2^32
+    (2.0**-24, 1 << 42, 46, None), # double precision, one wave per chunk (~256 hits)
 ]
 
 
