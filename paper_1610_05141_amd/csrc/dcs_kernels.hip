@@ -2108,6 +2108,8 @@ __global__ void k_reset(Control* ctl, Instance single, int has_single, Instance*
   }
 }
 
+// launch_zero runs 256-thread blocks; the first one clears every ticket word
+static_assert(kTicketWords <= 256, "one thread per ticket word in k_zero's first block");
 __global__ void k_zero(Control* ctl, unsigned long long* status, uint64_t n,
                        unsigned long long* tickets, unsigned int* err) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
