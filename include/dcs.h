@@ -462,6 +462,14 @@ int32_t dcs_debug_lookback_help(uint32_t polls);
  * kernel, more the work-group kernel (0 restores the default).  Never changes
  * a sample.  DCS_EINVAL above 8256 words. */
 int32_t dcs_debug_bernoulli_list(uint32_t words);
+/* dcs_debug_leaf_kernels -- test hook: which specialised leaf kernels a
+ * single-instance tree call leaves out, their leaves then run in the general
+ * work-group kernel: bit 0 the one-wave dense kernel, bit 1 the one-wave
+ * kernel of leaves of at most 1024 values, bit 2 the one-pass kernel of
+ * leaves expected to repeat.  By default (mask < 0) a call leaves out the
+ * kernels whose leaves its tree cannot plausibly hold.  Never changes a
+ * sample.  DCS_EINVAL for a mask above 7. */
+int32_t dcs_debug_leaf_kernels(int32_t mask);
 /* dcs_debug_plan -- the plan of a tree call (host only, no device work):
  * info[0] cut depth, [1] tree threads, [2] DFS stack entries per thread,
  * [3] leaf-job capacity, [4] the proven bound on leaf jobs, [5] 1 if the

@@ -18,7 +18,7 @@ __all__ = [
     "synchronize",
     "workspace_size", "bernoulli_capacity_hint", "Batch", "Online", "Server", "profile_enable",
     "profile_read", "profile_kinds", "debug_primitive", "debug_plan", "debug_leaf_capacity",
-    "debug_lookback_help", "debug_bernoulli_list",
+    "debug_lookback_help", "debug_bernoulli_list", "debug_leaf_kernels",
     "tune_set", "tune_get", "tune_reset",
     "EXPORTED_SYMBOLS", "LIB_PATH",
 ]
@@ -41,7 +41,8 @@ EXPORTED_SYMBOLS = (
     "dcs_server_submit_schedule", "dcs_server_poll", "dcs_server_release", "dcs_server_drain",
     "dcs_server_stats_read", "dcs_server_destroy", "dcs_server_now", "dcs_server_copy_out",
     "dcs_tune_set", "dcs_tune_get", "dcs_tune_reset", "dcs_debug_leaf_capacity",
-    "dcs_debug_plan", "dcs_debug_lookback_help", "dcs_debug_bernoulli_list", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
+    "dcs_debug_plan", "dcs_debug_lookback_help", "dcs_debug_bernoulli_list",
+    "dcs_debug_leaf_kernels", "dcs_online_create", "dcs_online_counts", "dcs_online_next",
     "dcs_online_destroy",
 )
 
@@ -137,6 +138,7 @@ def lib() -> ctypes.CDLL:
             "dcs_debug_plan": (i32, [i32, u64, u64, pp, ctypes.POINTER(u64)]),
             "dcs_debug_lookback_help": (i32, [u32]),
             "dcs_debug_bernoulli_list": (i32, [u32]),
+            "dcs_debug_leaf_kernels": (i32, [i32]),
             "dcs_online_create": (i32, [i32, u64, u64, u64, pp, u32, vp, ctypes.POINTER(vp)]),
             "dcs_online_counts": (i32, [vp, u64, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
             "dcs_online_next": (i32, [vp, u64, u64, vp, u64, ctypes.POINTER(u64), vp]),
@@ -467,6 +469,14 @@ def debug_lookback_help(polls: int) -> None:
     """Test hook: Bernoulli look-backs count a silent predecessor chunk
     themselves after `polls` polls (0: the default)."""
     _check(lib().dcs_debug_lookback_help(int(polls)), "dcs_debug_lookback_help")
+
+
+def debug_leaf_kernels(mask: int) -> None:
+    """Test hook: the specialised leaf kernels a single-instance tree call
+    leaves out (bit 0 dense, bit 1 small, bit 2 one-pass; their leaves then
+    run in the general work-group kernel); a negative mask restores the
+    default choice."""
+    _check(lib().dcs_debug_leaf_kernels(int(mask)), "dcs_debug_leaf_kernels")
 
 
 def debug_bernoulli_list(words: int) -> None:

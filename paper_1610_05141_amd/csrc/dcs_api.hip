@@ -118,6 +118,8 @@ std::atomic<uint32_t> g_debug_help_polls{0};
 // Test hook (dcs_debug_bernoulli_list): LDS positions per double-precision
 // chunk (0: from the chunk's expected hits).
 std::atomic<uint32_t> g_debug_bern_list{0};
+// Test hook (dcs_debug_leaf_kernels): forced mixed_takes mask, or -1.
+std::atomic<int32_t> g_debug_takes{-1};
 
 void leaf_capacity_exceeded() {
   uint32_t b = g_cap_boost.load();
@@ -447,6 +449,29 @@ void timing_end(hipStream_t s, Timing* t) {
   g_timings.push_back(*t);
 }
 
+// Leaf kinds that no leaf of a single instance's tree can have except by a
+// deviation of its counts from their expectations by tens of standard
+// deviations; their kernels are then not launched and k_leaf_mixed runs any
+// such leaf itself (the sample never depends on this).  A leaf's parent held
+// n0 or more values or a range above 2^32.  Dense leaves (dense_ratio n_v >=
+// N_v) then need some range of at most 2 dense_ratio n0 elements at density
+// 1/(2 dense_ratio), 64 times the sample's (kept below 1/(128 dense_ratio)).
+// Leaves of at most 1024 values need, when the range-forced levels end with
+// nodes of 2 n0 or more values and n0 = 4096, a split of such a node to leave
+// a quarter of its expected share.  One-pass leaves (n_v^2 >= 2 N_v with
+// n_v > 1024) need a density of 2/n0 or more, 16 times the sample's (kept
+// below 1/(32 n0)).
+uint32_t mixed_takes(const Instance& I) {
+  uint32_t forced = 0;
+  while (ceil_div_pow2(I.N, forced) > kLeafRange) ++forced;
+  const unsigned __int128 n = I.n, N = I.N;
+  uint32_t takes = 0;
+  if (I.variant == 1 || (I.n0 >= 1024 && n * 128u * I.dense_ratio < N)) takes |= dcs::kTakesDense;
+  if (I.n0 >= 4096 && (I.n >> forced) >= 2ull * I.n0) takes |= dcs::kTakesSmall;
+  if (I.variant == 1 || n * 32u * I.n0 < N) takes |= dcs::kTakesOnce;
+  return takes;
+}
+
 // Enqueue reset + tree + leaf for the instances already in the workspace.
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
@@ -476,6 +501,11 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   uint64_t want = static_cast<uint64_t>(c->cus) * std::max<uint32_t>(1, leaf_wgs_per_cu);
   if (c->leaf_grid > 0) want = static_cast<uint64_t>(c->leaf_grid);
   want = std::max<uint64_t>(1, std::min<uint64_t>(want, leaf_cap));
+  // batches launch every leaf kernel; a single instance skips those whose
+  // kinds its tree cannot plausibly hold
+  uint32_t takes = (single != nullptr && n_inst == 1) ? mixed_takes(*single) : 0u;
+  const int32_t forced_takes = g_debug_takes.load();
+  if (forced_takes >= 0 && single != nullptr && n_inst == 1) takes = static_cast<uint32_t>(forced_takes);
   Timing t4{}, t5{};
   timing_begin(2, s, &t2);
   timing_begin(4, s, &t4);
@@ -485,18 +515,18 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   if (e == hipSuccess) {
     timing_begin(5, s, &t5);
     e = dcs::launch_leaf(dcs::kLeafBack, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want),
-                         s);
+                         s, takes);
     timing_end(s, &t5);
   }
   Timing t13{};
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !(takes & dcs::kTakesOnce)) {
     timing_begin(13, s, &t13);
     e = dcs::launch_leaf(dcs::kLeafOnce, leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want),
                          s);
     timing_end(s, &t13);
   }
   Timing t6{};
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !(takes & dcs::kTakesDense)) {
     uint64_t waves = static_cast<uint64_t>(c->cus) * std::max(1, c->dense_occupancy);
     if (c->leaf_grid > 0) waves = static_cast<uint64_t>(c->leaf_grid) * (dcs::kLeafBlock / 64);
     waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, leaf_cap));
@@ -505,7 +535,7 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
     timing_end(s, &t6);
   }
   Timing t12{};
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !(takes & dcs::kTakesSmall)) {
     uint64_t waves = static_cast<uint64_t>(c->cus) * std::max(1, c->small_occupancy);
     if (c->leaf_grid > 0) waves = static_cast<uint64_t>(c->leaf_grid) * (dcs::kLeafBlock / 64);
     waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, leaf_cap));
@@ -520,7 +550,8 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
     e = dcs::launch_tree(inst, n_inst, threads, frontier, leaves, leaf_cap, stacks, stack_depth,
                          ctl, redo, 1, s);
   if (e == hipSuccess && redo != nullptr)
-    e = dcs::launch_leaf_round2(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s);
+    e = dcs::launch_leaf_round2(leaves, leaf_cap, out, ctl, static_cast<uint32_t>(want), s,
+                                takes);
   timing_end(s, &t2);
   if (e != hipSuccess) return DCS_EHIP;
   return DCS_OK;
@@ -1329,6 +1360,12 @@ int32_t dcs_debug_plan(int32_t variant, uint64_t n, uint64_t N, const dcs_params
 
 int32_t dcs_debug_lookback_help(uint32_t polls) {
   g_debug_help_polls.store(polls);
+  return DCS_OK;
+}
+
+int32_t dcs_debug_leaf_kernels(int32_t mask) {
+  if (mask > 7) return DCS_EINVAL;
+  g_debug_takes.store(mask < 0 ? -1 : mask);
   return DCS_OK;
 }
 

@@ -1524,14 +1524,17 @@ __device__ __forceinline__ uint64_t job_counts(const Control* ctl, int round) {
 // power-of-two ranges, except sparse ones expected to repeat) with only that
 // leaf body compiled in, so that the hot path keeps its values in registers.
 // kListBack: the back list with every other leaf body, leaving to the
-// one-wave kernels and to k_leaf_once the jobs they take; round2: the second
-// round's jobs (back list only, every kind, none left to the one-wave
-// kernels).  kListOnce: the back list's jobs of once_by_group, both rounds.
+// one-wave kernels and to k_leaf_once the jobs they take, except the kinds in
+// `takes` (kTakesDense / kTakesSmall / kTakesOnce: that kernel is not
+// launched); round2: the second round's jobs (back list only, every kind
+// but those of k_leaf_once, which it takes too when kTakesOnce is set).
+// kListOnce: the back list's jobs of once_by_group, both rounds.
 constexpr int kListFront = 0, kListBack = 1, kListOnce = 2;
 
 template <int B, int kList>
 __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint64_t leaf_cap,
-                                          uint64_t* out, Control* ctl, int round2 = 0) {
+                                          uint64_t* out, Control* ctl, int round2 = 0,
+                                          uint32_t takes = 0) {
   constexpr bool kPow2 = kList == kListFront;
   __shared__ uint32_t smem[kSmemWords];
   LeafSmem sm;
@@ -1591,7 +1594,9 @@ __device__ __forceinline__ void leaf_loop(const Leaf* __restrict__ leaves, uint6
             if (kList == kListOnce)
               run = once_by_group(c);
             else
-              run = !once_by_group(c) && (round2 || (!dense_by_wave(c) && !small_by_wave(c)));
+              run = (!once_by_group(c) || (takes & kTakesOnce)) &&
+                    (round2 || ((!dense_by_wave(c) || (takes & kTakesDense)) &&
+                                (!small_by_wave(c) || (takes & kTakesSmall))));
           }
           const unsigned long long m = __ballot(run);
           if (tid == 0) sm.scr[kScrKeep] = static_cast<uint32_t>(m);
@@ -1655,8 +1660,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_l
 
 template <int B>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(6))) void k_leaf_mixed(
-    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl, int round2) {
-  leaf_loop<B, kListBack>(leaves, leaf_cap, out, ctl, round2);
+    const Leaf* __restrict__ leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl, int round2,
+    uint32_t takes) {
+  leaf_loop<B, kListBack>(leaves, leaf_cap, out, ctl, round2, takes);
 }
 
 template <int B>
@@ -3022,13 +3028,13 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
 }
 
 hipError_t launch_leaf(int which, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
-                       Control* ctl, uint32_t grid, hipStream_t stream) {
+                       Control* ctl, uint32_t grid, hipStream_t stream, uint32_t takes) {
   if (which == kLeafFront)
     hipLaunchKernelGGL(k_leaf_pow2<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                        leaf_cap, out, ctl);
   else if (which == kLeafBack)
     hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
-                       leaf_cap, out, ctl, 0);
+                       leaf_cap, out, ctl, 0, takes);
   else if (which == kLeafOnce)
     hipLaunchKernelGGL(k_leaf_once<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                        leaf_cap, out, ctl, 0);
@@ -3038,11 +3044,11 @@ hipError_t launch_leaf(int which, const Leaf* leaves, uint64_t leaf_cap, uint64_
 }
 
 hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
-                              uint32_t grid, hipStream_t stream) {
+                              uint32_t grid, hipStream_t stream, uint32_t takes) {
   hipLaunchKernelGGL(k_leaf_mixed<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
-                     leaf_cap, out, ctl, 1);
+                     leaf_cap, out, ctl, 1, takes & kTakesOnce);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || (takes & kTakesOnce)) return e;
   hipLaunchKernelGGL(k_leaf_once<kLeafBlock>, dim3(grid), dim3(kLeafBlock), 0, stream, leaves,
                      leaf_cap, out, ctl, 1);
   return hipGetLastError();

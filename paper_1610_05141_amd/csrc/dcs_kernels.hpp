@@ -169,13 +169,19 @@ hipError_t launch_tree(const Instance* inst, uint32_t n_inst, uint64_t total_thr
 // takes; kLeafOnce = the back list's sparse leaves of more than 1024 values
 // with n_v^2 >= 2 N_v (one-pass sampler).
 constexpr int kLeafFront = 0, kLeafBack = 1, kLeafOnce = 2;
+// Kinds that k_leaf_mixed runs itself because their own kernel is not
+// launched (never changes a sample): dense leaves over ranges up to 2^16,
+// sparse and with-replacement leaves of at most 1024 values, the one-pass
+// sparse leaves.
+constexpr uint32_t kTakesDense = 1, kTakesSmall = 2, kTakesOnce = 4;
 hipError_t launch_leaf(int which, const Leaf* leaves, uint64_t leaf_cap, uint64_t* out,
-                       Control* ctl, uint32_t grid, hipStream_t stream);
+                       Control* ctl, uint32_t grid, hipStream_t stream, uint32_t takes = 0);
 // The second round's jobs (all on the back list, every kind run by the
-// work-group kernels of the back list); returns at once when round 0 handed
-// over every leaf.
+// work-group kernels of the back list; k_leaf_once's too when `takes` has
+// kTakesOnce, which then is not launched); returns at once when round 0
+// handed over every leaf.
 hipError_t launch_leaf_round2(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,
-                              uint32_t grid, hipStream_t stream);
+                              uint32_t grid, hipStream_t stream, uint32_t takes = 0);
 // Dense leaves of the back list whose range fits 16-bit positions, one wave
 // per leaf (k_leaf_mixed skips them).
 hipError_t launch_leaf_dense(const Leaf* leaves, uint64_t leaf_cap, uint64_t* out, Control* ctl,

@@ -86,7 +86,10 @@ def test_tuning_table_geometry_invariance(ref):
 def test_profile_kinds_times_only_the_selected_kernels():
     """dcs_profile_kinds: with only kind 4 selected, a sample records launches
     of the power-of-two leaf kernel and none of the tree or the other leaf
-    kernels; with every kind selected, all of them."""
+    kernels; with every kind selected and every leaf kernel launched, all of
+    them.  By default this sparse sample (density 2^-18) launches no
+    one-wave dense, one-wave small or one-pass kernel: its tree cannot
+    plausibly hold their leaves."""
     m = dcs()
     announce("profile kinds")
     n, N = 1 << 18, 1 << 36
@@ -98,10 +101,18 @@ def test_profile_kinds_times_only_the_selected_kernels():
         assert m.profile_read(4)[1] == 1
         assert all(m.profile_read(k)[1] == 0 for k in (0, 1, 2, 5, 6))
         m.profile_kinds(None)
+        m.debug_leaf_kernels(0)
         m.profile_enable(True)
         m.sample(n, N, 5)
         m.synchronize()
-        assert all(m.profile_read(k)[1] == 1 for k in (0, 1, 2, 4, 5, 6))
+        assert all(m.profile_read(k)[1] == 1 for k in (0, 1, 2, 4, 5, 6, 12, 13))
+        m.debug_leaf_kernels(-1)
+        m.profile_enable(True)
+        m.sample(n, N, 5)
+        m.synchronize()
+        assert all(m.profile_read(k)[1] == 1 for k in (0, 1, 2, 4, 5))
+        assert all(m.profile_read(k)[1] == 0 for k in (6, 12, 13))
     finally:
+        m.debug_leaf_kernels(-1)
         m.profile_kinds(None)
         m.profile_enable(False)

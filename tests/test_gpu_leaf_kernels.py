@@ -1,0 +1,51 @@
+"""Which leaf kernels run never changes a sample (Sec. 4.5: the result is a
+function of the input alone).  A single-instance call leaves out the
+specialised leaf kernels (one-wave dense, one-wave small, one-pass) whose
+leaves its tree cannot plausibly hold, and the general work-group kernel then
+runs any such leaf itself.  The test hook forces the choice: every kind of
+leaf is sampled once by its own kernel (mask 0) and once by the general
+kernel (mask 7), and by default; all against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import announce, dcs, first_mismatch, to_np_u64
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (variant, n, N, seed, n0): the leaf kind the case is made of
+    (0, 1 << 20, 1 << 21, 61, 4096),              # dense leaves over ranges below 2^16
+    (0, 200_000, 10**9 + 7, 62, 512),             # sparse leaves of 256-511 values
+    (1, 200_000, 10**9 + 7, 63, 512),             # with-replacement leaves of 256-511
+    (0, 1 << 20, 20 * (1 << 20) + 12345, 64, 4096),  # sparse leaves expected to repeat
+    (0, 1 << 22, 1 << 40, 65, 4096),              # power-of-two ranges (front list)
+    (1, 300_000, 3, 66, 4096),                    # constant leaves cut into pieces
+]
+
+
+@pytest.fixture
+def m():
+    mod = dcs()
+    yield mod
+    mod.debug_leaf_kernels(-1)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_leaf_kernel_choice_never_changes_the_sample(ref, m, case):
+    variant, n, N, seed, n0 = CASES[case]
+    want = ref.replacement(n, N, seed, n0=n0) if variant else ref.sample(n, N, seed, n0=n0)
+    for mask in (0, 7, -1):
+        m.debug_leaf_kernels(mask)
+        announce(f"leaf kernels mask {mask}: variant={variant} n={n} N={N} seed={seed} n0={n0}")
+        f = m.sample_replacement if variant else m.sample
+        out = f(n, N, seed, n0=n0)
+        m.synchronize()
+        got = to_np_u64(out)
+        assert np.array_equal(got, want), (mask, first_mismatch(got, want))
+
+
+def test_leaf_kernel_mask_rejected_above_limit():
+    mod = dcs()
+    with pytest.raises(mod.DcsError):
+        mod.debug_leaf_kernels(8)
+    mod.debug_leaf_kernels(-1)
