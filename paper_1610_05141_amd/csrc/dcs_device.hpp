@@ -295,12 +295,20 @@ constexpr double kD1 = 0x1.b72cd3f331398p+0;  // 2 sqrt(2/e)
 constexpr double kD2 = 0x1.cc3ebd3bc711ap-1;  // 3 - 2 sqrt(3/e)
 constexpr uint64_t kInversionMax = 16;
 
-// Accept/reject for 2 ln U <= T with the two squeezes.
-__device__ __forceinline__ bool rou_accept(double u, double T, bool* reject) {
+// 2 ln U, computed before T so that its dependent chain overlaps T's (the
+// wave waits for its slowest lane, and some lane of a wave usually needs it).
+__device__ __forceinline__ double rou_log2u(double u) {
+  double l = 2.0 * log64(u);
+  asm volatile("" : "+v"(l));  // keep it here, not sunk into the test below
+  return l;
+}
+
+// Accept/reject for 2 ln U <= T with the two squeezes; lu2 = rou_log2u(u).
+__device__ __forceinline__ bool rou_accept(double u, double T, double lu2, bool* reject) {
   *reject = false;
   if (u * (4.0 - u) - 3.0 <= T) return true;
   if (u * (u - T) >= 1.0) { *reject = true; return false; }
-  return 2.0 * log64(u) <= T;
+  return lu2 <= T;
 }
 
 // The ratio-of-uniforms loop: attempt a takes draws 2a (U) and 2a+1 (V),
@@ -387,13 +395,14 @@ __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N,
     const double x = a + (s * (v - 0.5)) / u;
     if (x < 0.0 || x >= kmax_d) return false;
     const uint64_t k = static_cast<uint64_t>(floor(x));
+    const double lu2 = rou_log2u(u);
     double T = lnfact_diff(mode, k);
     T = T + lnfact_diff(M - mode, M - k);
     T = T + lnfact_diff(n - mode, n - k);
     T = T + lnfact_diff(rest + mode, rest + k);
     bool rej;
     *out = k;
-    return rou_accept(u, T, &rej);
+    return rou_accept(u, T, lu2, &rej);
   });
 }
 
@@ -457,12 +466,13 @@ __device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t 
     const double x = a + (s * (v - 0.5)) / u;
     if (x < 0.0 || x >= kmax_d) return false;
     const uint64_t k = static_cast<uint64_t>(floor(x));
+    const double lu2 = rou_log2u(u);
     double T = static_cast<double>(static_cast<int64_t>(k) - static_cast<int64_t>(mode)) * lodds;
     T = T + lnfact_diff(mode, k);
     T = T + lnfact_diff(n - mode, n - k);
     bool rej;
     *out = k;
-    return rou_accept(u, T, &rej);
+    return rou_accept(u, T, lu2, &rej);
   });
 }
 
