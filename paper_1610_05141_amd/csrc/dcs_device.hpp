@@ -311,13 +311,30 @@ __device__ __forceinline__ bool rou_accept(double u, double T, double lu2, bool*
   return lu2 <= T;
 }
 
+// Broadcast of lane j's value within each aligned quad of lanes (DPP
+// quad_perm), for a double.
+template <int j>
+__device__ __forceinline__ double quad_lane(double x) {
+  constexpr int ctrl = j | (j << 2) | (j << 4) | (j << 6);
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+  const uint32_t lo = static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(b), ctrl, 0xf, 0xf, false));
+  const uint32_t hi = static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), ctrl, 0xf, 0xf, false));
+  return __longlong_as_double(static_cast<long long>(static_cast<uint64_t>(lo) |
+                                                     (static_cast<uint64_t>(hi) << 32)));
+}
+
 // The ratio-of-uniforms loop: attempt a takes draws 2a (U) and 2a+1 (V),
 // i.e. Philox block a, and the deviate is the first accepted attempt.
 // kWave: the lanes of a wave form aligned groups of G = 2^d.gbits lanes
-// (the whole wave when gbits = 6), each group sampling one deviate; lane r
-// of a group tries attempt G*j + r in round j, and the group takes its
-// lowest accepted attempt (the same deviate, found in one round instead of
-// one attempt after another).
+// (the whole wave when gbits = 6), each group sampling one deviate, and the
+// group takes its lowest accepted attempt (the same deviate, found in one
+// round instead of one attempt after another).  With G >= 4 each aligned
+// quad of lanes shares one attempt (quad q of a group: attempt G/4 * j + q
+// in round j) and its lanes compute the attempt's ln-factorial terms side by
+// side (attempt(u, v, sub, true, &k), sub = lane mod 4); with G = 2 each
+// lane tries one attempt (attempt 2j + r in round j).
 template <bool kWave, class Attempt>
 __device__ __forceinline__ uint64_t rou_first_accepted(Draws64& d, Attempt attempt) {
   if constexpr (kWave) {
@@ -327,12 +344,15 @@ __device__ __forceinline__ uint64_t rou_first_accepted(Draws64& d, Attempt attem
     const uint32_t r = lane & (size - 1u);
     const uint32_t base = lane - r;
     const unsigned long long gmask = d.gbits >= 6 ? ~0ull : (1ull << size) - 1ull;
+    const bool quad = size >= 4;
+    const uint32_t per_round = quad ? size >> 2 : size;
+    const uint32_t slot = quad ? r >> 2 : r;
     for (uint32_t round = 0;; ++round) {
-      const uint4 b = philox_block(d.s, round * size + r);
+      const uint4 b = philox_block(d.s, round * per_round + slot);
       const double u = unit_open0(static_cast<uint64_t>(b.x) | (static_cast<uint64_t>(b.y) << 32));
       const double v = unit_closed0(static_cast<uint64_t>(b.z) | (static_cast<uint64_t>(b.w) << 32));
       uint64_t k = 0;
-      const bool ok = attempt(u, v, &k);
+      const bool ok = attempt(u, v, static_cast<int>(lane & 3u), quad, &k);
       const unsigned long long m = (__ballot(ok) >> base) & gmask;
       if (m != 0) {
         const uint32_t f = static_cast<uint32_t>(__ffsll(static_cast<long long>(m)) - 1);
@@ -352,7 +372,7 @@ __device__ __forceinline__ uint64_t rou_first_accepted(Draws64& d, Attempt attem
       const double u = unit_open0(d.next());
       const double v = unit_closed0(d.next());
       uint64_t k = 0;
-      if (attempt(u, v, &k)) return k;
+      if (attempt(u, v, 0, false, &k)) return k;
     }
   }
 }
@@ -391,15 +411,37 @@ __device__ __forceinline__ uint64_t hyp_core(uint64_t n, uint64_t M, uint64_t N,
   if (kcap < static_cast<double>(kmax)) kmax = static_cast<uint64_t>(kcap);
   const double kmax_d = static_cast<double>(kmax);
   const uint64_t rest = N - M - n;
-  return rou_first_accepted<kWave>(d, [&](double u, double v, uint64_t* out) {
+  return rou_first_accepted<kWave>(d, [&](double u, double v, int sub, bool quad,
+                                          uint64_t* out) {
     const double x = a + (s * (v - 0.5)) / u;
-    if (x < 0.0 || x >= kmax_d) return false;
+    if (x < 0.0 || x >= kmax_d) return false;  // the same in every lane of a quad
     const uint64_t k = static_cast<uint64_t>(floor(x));
     const double lu2 = rou_log2u(u);
-    double T = lnfact_diff(mode, k);
-    T = T + lnfact_diff(M - mode, M - k);
-    T = T + lnfact_diff(n - mode, n - k);
-    T = T + lnfact_diff(rest + mode, rest + k);
+    double T;
+    if (quad) {
+      // term `sub` in this lane, then the sum in the sequential order
+      uint64_t ta, tb;
+      if (sub == 0) {
+        ta = mode;
+        tb = k;
+      } else if (sub == 1) {
+        ta = M - mode;
+        tb = M - k;
+      } else if (sub == 2) {
+        ta = n - mode;
+        tb = n - k;
+      } else {
+        ta = rest + mode;
+        tb = rest + k;
+      }
+      const double t = lnfact_diff(ta, tb);
+      T = ((quad_lane<0>(t) + quad_lane<1>(t)) + quad_lane<2>(t)) + quad_lane<3>(t);
+    } else {
+      T = lnfact_diff(mode, k);
+      T = T + lnfact_diff(M - mode, M - k);
+      T = T + lnfact_diff(n - mode, n - k);
+      T = T + lnfact_diff(rest + mode, rest + k);
+    }
     bool rej;
     *out = k;
     return rou_accept(u, T, lu2, &rej);
@@ -462,14 +504,22 @@ __device__ __forceinline__ uint64_t binom_core(uint64_t n, uint64_t l, uint64_t 
   const double lodds = log1p64(
       static_cast<double>(static_cast<int64_t>(2 * l) - static_cast<int64_t>(Nv)) /
       static_cast<double>(r));
-  return rou_first_accepted<kWave>(d, [&](double u, double v, uint64_t* out) {
+  return rou_first_accepted<kWave>(d, [&](double u, double v, int sub, bool quad,
+                                          uint64_t* out) {
     const double x = a + (s * (v - 0.5)) / u;
-    if (x < 0.0 || x >= kmax_d) return false;
+    if (x < 0.0 || x >= kmax_d) return false;  // the same in every lane of a quad
     const uint64_t k = static_cast<uint64_t>(floor(x));
     const double lu2 = rou_log2u(u);
     double T = static_cast<double>(static_cast<int64_t>(k) - static_cast<int64_t>(mode)) * lodds;
-    T = T + lnfact_diff(mode, k);
-    T = T + lnfact_diff(n - mode, n - k);
+    if (quad) {
+      // lanes 0 and 1 of the quad: one ln-factorial term each
+      const double t = sub == 0 ? lnfact_diff(mode, k) : sub == 1 ? lnfact_diff(n - mode, n - k)
+                                                                  : 0.0;
+      T = (T + quad_lane<0>(t)) + quad_lane<1>(t);
+    } else {
+      T = T + lnfact_diff(mode, k);
+      T = T + lnfact_diff(n - mode, n - k);
+    }
     bool rej;
     *out = k;
     return rou_accept(u, T, lu2, &rej);
