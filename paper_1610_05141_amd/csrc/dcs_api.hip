@@ -858,6 +858,10 @@ int32_t dcs_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, const dcs_p
   const float c32 = full ? 0.0f : static_cast<float>(1.0 / host_log1p_series(-rho));
   const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(
       1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->wb_occupancy)));
+  // the first repair round's words (at most hi - n) over 256-thread groups,
+  // four words per thread
+  const uint32_t repair_grid = static_cast<uint32_t>(std::max<uint64_t>(
+      1, std::min<uint64_t>(static_cast<uint64_t>(c->cus) * 4, (hi - n + 1023) / 1024)));
   hipError_t e = dcs::launch_wb_zero(ctl, b, n_chunks, error_word(c, stream), s);
   // Two attempts are enqueued; the second one's kernels return at once when
   // the first is accepted (a rejection has probability below about 1e-11).
@@ -868,7 +872,7 @@ int32_t dcs_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, const dcs_p
     timing_end(s, &t9);
     if (e != hipSuccess) break;
     timing_begin(10, s, &t10);
-    e = dcs::launch_wb_mid(n, seed, n_chunks, a, a == 1 ? 1 : 0, b, ctl, s);
+    e = dcs::launch_wb_mid(n, seed, n_chunks, a, a == 1 ? 1 : 0, b, ctl, repair_grid, s);
     timing_end(s, &t10);
     if (e != hipSuccess) break;
     timing_begin(11, s, &t11);

@@ -2659,6 +2659,8 @@ __global__ void k_wb_zero(Control* ctl, WbBuffers b, unsigned int* err) {
   if (i0 == 0) {
     b.state->accepted = 0;
     b.state->hits = 0;
+    b.state->pending = 0;
+    b.state->fresh = 0;
     start_control(ctl, err);
   }
 }
@@ -2728,18 +2730,24 @@ __device__ uint64_t wg_scan_tiles(const uint32_t* x, TOut* y, uint64_t count, ui
   return carry;
 }
 
-// One work-group: hit offsets of the chunks (scan of the counts), the
-// acceptance test, and the repair.  The removed hit indices are the first
-// r = n' - n distinct non-void values of the (0, WREPAIR, attempt) words
-// mapped into [0, n'), found in rounds (each round takes as many more words
-// as values are missing; a word adds at most one new value, so the rounds
-// stop exactly where the sequential rule does); a value is new iff its
-// bitmap bit was clear, and then its block's removal count goes up.  Last,
-// the removal counts per block become their exclusive prefix.
+// The scan / acceptance / repair step of an attempt, in three kernels.
+// k_wb_mid (one work-group): hit offsets of the chunks (scan of the counts)
+// and the acceptance test; an accepted attempt is marked pending.  The
+// removed hit indices are the first r = n' - n distinct non-void values of
+// the (0, WREPAIR, attempt) words mapped into [0, n'), found in rounds (each
+// round takes as many more words as values are missing; a word adds at most
+// one new value, so the rounds stop exactly where the sequential rule does);
+// a value is new iff its bitmap bit was clear, and then its block's removal
+// count goes up.  k_wb_repair1 (many work-groups) takes the first round,
+// words [0, r): the bitmap makes the set of new values and their count
+// independent of the order of the words' atomics.  k_wb_finish (one
+// work-group) takes the later rounds from word r, turns the removal counts
+// per block into their exclusive prefix and marks the attempt accepted.
 __global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t seed,
                                                         uint64_t n_chunks, uint32_t attempt,
                                                         int last, WbBuffers b, Control* ctl) {
   __shared__ uint64_t scr[kWbMidBlock / 64];
+  (void)seed;
   if (b.state->accepted != 0) return;
   const uint32_t tid = threadIdx.x;
   const uint64_t hits = wg_scan_tiles(b.cnt, b.off, n_chunks, scr);
@@ -2748,11 +2756,57 @@ __global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t see
     if (last && tid == 0) atomicOr(ctl->err, kErrRestartLimit);
     return;
   }
+  if (tid == 0) {
+    b.state->hits = hits;
+    b.state->pending = attempt + 1;
+  }
+}
+
+// The first repair round of a pending attempt over the whole grid; each wave
+// adds its count of new values to state->fresh.
+__global__ __launch_bounds__(256) void k_wb_repair1(uint64_t n, uint64_t seed, uint32_t attempt,
+                                                    WbBuffers b) {
+  if (b.state->accepted != 0 || b.state->pending != attempt + 1) return;
+  const uint64_t hits = b.state->hits;
   const uint64_t r = hits - n;
-  if (r > 0) {
+  const Stream st = make_stream(seed, 0, kWRepair, attempt);
+  const uint32_t thr = range_threshold(hits);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint32_t fresh = 0;
+  for (uint64_t blk = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; (blk << 2) < r;
+       blk += stride) {
+    const uint4 w = philox_block(st, static_cast<uint32_t>(blk));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t tk = (blk << 2) + k;
+      uint32_t v;
+      if (tk < r && range_map(pick(w, k), hits, thr, &v)) {
+        const unsigned long long bit = 1ull << (v & 63u);
+        const unsigned long long old = atomicOr(&b.bitmap[v >> 6], bit);
+        if ((old & bit) == 0) {
+          ++fresh;
+          atomicAdd(&b.rem[v >> kWbRemShift], 1u);
+        }
+      }
+    }
+  }
+  const uint32_t sum = __builtin_amdgcn_readlane(wave_scan_incl(fresh), 63);
+  if ((threadIdx.x & 63u) == 0 && sum != 0)
+    atomicAdd(&b.state->fresh, static_cast<unsigned long long>(sum));
+}
+
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_finish(uint64_t n, uint64_t seed,
+                                                           uint32_t attempt, WbBuffers b) {
+  __shared__ uint64_t scr[kWbMidBlock / 64];
+  if (b.state->accepted != 0 || b.state->pending != attempt + 1) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t hits = b.state->hits;
+  const uint64_t r = hits - n;
+  uint64_t d = b.state->fresh;  // new values of the first round, words [0, r)
+  if (d < r) {
     const Stream st = make_stream(seed, 0, kWRepair, attempt);
     const uint32_t thr = range_threshold(hits);
-    uint64_t d = 0, t = 0;
+    uint64_t t = r;
     while (d < r) {
       const uint64_t t1 = t + (r - d);
       uint64_t fresh = 0;
@@ -2780,10 +2834,7 @@ __global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t see
   }
   __syncthreads();
   (void)wg_scan_tiles(b.rem, b.rem, (hits + (1u << kWbRemShift) - 1) >> kWbRemShift, scr);
-  if (tid == 0) {
-    b.state->hits = hits;
-    b.state->accepted = attempt + 1;
-  }
+  if (tid == 0) b.state->accepted = attempt + 1;
 }
 
 // Write pass: chunk j again, group by group.  Its hits have global indices
@@ -3120,9 +3171,16 @@ hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n
 }
 
 hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
-                         const WbBuffers& b, Control* ctl, hipStream_t stream) {
+                         const WbBuffers& b, Control* ctl, uint32_t repair_grid,
+                         hipStream_t stream) {
   hipLaunchKernelGGL(k_wb_mid, dim3(1), dim3(kWbMidBlock), 0, stream, n, seed, n_chunks, attempt,
                      last, b, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wb_repair1, dim3(repair_grid), dim3(256), 0, stream, n, seed, attempt, b);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wb_finish, dim3(1), dim3(kWbMidBlock), 0, stream, n, seed, attempt, b);
   return hipGetLastError();
 }
 

@@ -219,8 +219,10 @@ hipError_t launch_segments(Instance* inst, uint64_t K, uint32_t D, uint64_t n, u
 // Whole-range Algorithm B: the state word of a call (attempt + 1 once an
 // attempt is accepted, else 0) and its accepted hit count.
 struct WbState {
-  unsigned long long accepted;
+  unsigned long long accepted;  // attempt + 1 once accepted and repaired
   unsigned long long hits;
+  unsigned long long pending;   // attempt + 1 once it passed the acceptance test
+  unsigned long long fresh;     // new values found by the first repair round
 };
 // Removal counts are kept per block of 2^kWbRemShift hit indices.
 constexpr uint32_t kWbRemShift = 12;
@@ -247,7 +249,8 @@ hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n
                            int full, uint32_t attempt, const WbBuffers& b, uint32_t grid,
                            hipStream_t stream);
 hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
-                         const WbBuffers& b, Control* ctl, hipStream_t stream);
+                         const WbBuffers& b, Control* ctl, uint32_t repair_grid,
+                         hipStream_t stream);
 hipError_t launch_wb_write(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
                            int full, uint32_t attempt, const WbBuffers& b, uint64_t* out,
                            uint32_t grid, hipStream_t stream);
