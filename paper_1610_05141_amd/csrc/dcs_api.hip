@@ -613,7 +613,7 @@ struct BernLayout {
 // chunk offsets (u64) | removal counts per block of hit indices (u32) |
 // removal bitmap (u64 words).
 struct WbLayout {
-  size_t ctl = 0, state = 0, cnt = 0, off = 0, rem = 0, bitmap = 0, total = 0;
+  size_t ctl = 0, state = 0, cnt = 0, off = 0, rem = 0, bitmap = 0, tsum = 0, total = 0;
 };
 
 WbLayout wb_layout(uint64_t n_chunks, uint64_t rem_blocks, uint64_t words) {
@@ -631,6 +631,8 @@ WbLayout wb_layout(uint64_t n_chunks, uint64_t rem_blocks, uint64_t words) {
   o = align_up(o + sizeof(uint32_t) * rem_blocks);
   L.bitmap = o;
   o = align_up(o + sizeof(uint64_t) * words);
+  L.tsum = o;
+  o = align_up(o + sizeof(uint64_t) * dcs::kWbTileSums);
   L.total = o;
   return L;
 }
@@ -855,6 +857,7 @@ int32_t dcs_sample_wholerange(uint64_t n, uint64_t N, uint64_t seed, const dcs_p
   b.rem_blocks = rem_blocks;
   b.bitmap = reinterpret_cast<unsigned long long*>(base + L.bitmap);
   b.words = words;
+  b.tsum = reinterpret_cast<uint64_t*>(base + L.tsum);
   const float c32 = full ? 0.0f : static_cast<float>(1.0 / host_log1p_series(-rho));
   const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(
       1, std::min<uint64_t>(n_chunks, static_cast<uint64_t>(c->cus) * c->wb_occupancy)));

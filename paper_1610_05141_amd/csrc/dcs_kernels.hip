@@ -2702,37 +2702,10 @@ __global__ __launch_bounds__(64) void k_wb_count(uint64_t N, uint64_t seed, uint
   }
 }
 
-// Exclusive prefix sums of x[0..count) into y (may be x), by one work-group
-// in tiles of 4 kWbMidBlock entries: thread t loads entries 4t..4t+3 of the
-// tile (coalesced), one block scan per tile, carry across tiles.  Returns
-// the total.
-template <typename TOut>
-__device__ uint64_t wg_scan_tiles(const uint32_t* x, TOut* y, uint64_t count, uint64_t* scr) {
-  constexpr uint64_t kTile = 4 * kWbMidBlock;
-  const uint32_t tid = threadIdx.x;
-  uint64_t carry = 0;
-  for (uint64_t t0 = 0; t0 < count; t0 += kTile) {
-    const uint64_t i = t0 + 4u * tid;
-    uint32_t v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = i + k < count ? x[i + k] : 0u;
-    const uint64_t s = static_cast<uint64_t>(v[0]) + v[1] + v[2] + v[3];
-    uint64_t total;
-    uint64_t run = carry + block_scan_excl<kWbMidBlock, uint64_t>(s, scr, &total);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i + k < count) y[i + k] = static_cast<TOut>(run);
-      run += v[k];
-    }
-    carry += total;
-  }
-  __syncthreads();
-  return carry;
-}
-
-// The scan / acceptance / repair step of an attempt, in three kernels.
-// k_wb_mid (one work-group): hit offsets of the chunks (scan of the counts)
-// and the acceptance test; an accepted attempt is marked pending.  The
+// The scan / acceptance / repair step of an attempt.  The chunk counts'
+// exclusive prefix (each chunk's first hit index) and the hit total come
+// from a tiled scan (k_wb_tile_sums, k_wb_mid, k_wb_tile_apply); k_wb_mid
+// also takes the acceptance test and marks an accepted attempt pending.  The
 // removed hit indices are the first r = n' - n distinct non-void values of
 // the (0, WREPAIR, attempt) words mapped into [0, n'), found in rounds (each
 // round takes as many more words as values are missing; a word adds at most
@@ -2741,16 +2714,75 @@ __device__ uint64_t wg_scan_tiles(const uint32_t* x, TOut* y, uint64_t count, ui
 // count goes up.  k_wb_repair1 (many work-groups) takes the first round,
 // words [0, r): the bitmap makes the set of new values and their count
 // independent of the order of the words' atomics.  k_wb_finish (one
-// work-group) takes the later rounds from word r, turns the removal counts
-// per block into their exclusive prefix and marks the attempt accepted.
-__global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t seed,
-                                                        uint64_t n_chunks, uint32_t attempt,
-                                                        int last, WbBuffers b, Control* ctl) {
+// work-group) takes the later rounds from word r and marks the attempt
+// accepted; a second tiled scan (k_wb_tile_sums, k_wb_rem_top,
+// k_wb_tile_apply) turns the removal counts per block into their exclusive
+// prefix before the write pass.
+
+// Per-tile sums of x[0..count) (tile = one work-group of kWbMidBlock
+// threads, 4 entries each).  after = 0: runs while no attempt is accepted;
+// after = 1: runs for the accepted attempt `attempt`.
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_tile_sums(const uint32_t* x, uint64_t count,
+                                                              uint64_t* sums, WbBuffers b,
+                                                              uint32_t attempt, int after) {
   __shared__ uint64_t scr[kWbMidBlock / 64];
-  (void)seed;
+  static_assert(kWbTile == 4 * kWbMidBlock, "four entries per thread");
+  if (after ? b.state->accepted != attempt + 1 : b.state->accepted != 0) return;
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kWbTile + 4u * threadIdx.x;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += i + k < count ? x[i + k] : 0u;
+  uint64_t total;
+  (void)block_scan_excl<kWbMidBlock, uint64_t, false>(s, scr, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// y[i] = exclusive prefix of x at i: the tile's own scan plus its sum's
+// prefix (sums already scanned).  after = 0: the attempt that passed the
+// acceptance test; after = 1: the accepted attempt.  x may be y.
+template <typename TOut>
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_tile_apply(const uint32_t* x, TOut* y,
+                                                               uint64_t count,
+                                                               const uint64_t* sums, WbBuffers b,
+                                                               uint32_t attempt, int after) {
+  __shared__ uint64_t scr[kWbMidBlock / 64];
+  if (after ? b.state->accepted != attempt + 1
+            : (b.state->accepted != 0 || b.state->pending != attempt + 1))
+    return;
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kWbTile + 4u * threadIdx.x;
+  uint32_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = i + k < count ? x[i + k] : 0u;
+  const uint64_t s = static_cast<uint64_t>(v[0]) + v[1] + v[2] + v[3];
+  uint64_t total;
+  uint64_t run = sums[blockIdx.x] + block_scan_excl<kWbMidBlock, uint64_t, false>(s, scr, &total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i + k < count) y[i + k] = static_cast<TOut>(run);
+    run += v[k];
+  }
+}
+
+// Exclusive scan of sums[0..tiles) in place (one work-group, tiles <=
+// kWbMidBlock); returns the total in every thread.
+__device__ uint64_t wb_scan_sums(uint64_t* sums, uint32_t tiles, uint64_t* scr) {
+  const uint32_t tid = threadIdx.x;
+  const uint64_t v = tid < tiles ? sums[tid] : 0;
+  uint64_t total;
+  const uint64_t e = block_scan_excl<kWbMidBlock, uint64_t>(v, scr, &total);
+  if (tid < tiles) sums[tid] = e;
+  return total;
+}
+
+// Scan of the chunks' tile sums and the acceptance test (one work-group);
+// an accepted attempt is marked pending with its hit count.
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint32_t tiles,
+                                                        uint32_t attempt, int last, WbBuffers b,
+                                                        Control* ctl) {
+  __shared__ uint64_t scr[kWbMidBlock / 64];
   if (b.state->accepted != 0) return;
   const uint32_t tid = threadIdx.x;
-  const uint64_t hits = wg_scan_tiles(b.cnt, b.off, n_chunks, scr);
+  const uint64_t hits = wb_scan_sums(b.tsum, tiles, scr);
   const uint64_t hi = n + 16 * isqrt64(n) + 64;
   if (hits < n || hits > hi) {  // the same decision in every thread
     if (last && tid == 0) atomicOr(ctl->err, kErrRestartLimit);
@@ -2760,6 +2792,14 @@ __global__ __launch_bounds__(kWbMidBlock) void k_wb_mid(uint64_t n, uint64_t see
     b.state->hits = hits;
     b.state->pending = attempt + 1;
   }
+}
+
+// Scan of the removal counts' tile sums for the accepted attempt.
+__global__ __launch_bounds__(kWbMidBlock) void k_wb_rem_top(uint32_t tiles, uint32_t attempt,
+                                                            WbBuffers b) {
+  __shared__ uint64_t scr[kWbMidBlock / 64];
+  if (b.state->accepted != attempt + 1) return;
+  (void)wb_scan_sums(b.tsum + kWbMaxTiles, tiles, scr);
 }
 
 // The first repair round of a pending attempt over the whole grid; each wave
@@ -2832,9 +2872,7 @@ __global__ __launch_bounds__(kWbMidBlock) void k_wb_finish(uint64_t n, uint64_t 
       t = t1;
     }
   }
-  __syncthreads();
-  (void)wg_scan_tiles(b.rem, b.rem, (hits + (1u << kWbRemShift) - 1) >> kWbRemShift, scr);
-  if (tid == 0) b.state->accepted = attempt + 1;
+  if (tid == 0) b.state->accepted = attempt + 1;  // the removal counts are final
 }
 
 // Write pass: chunk j again, group by group.  Its hits have global indices
@@ -3173,14 +3211,22 @@ hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n
 hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
                          const WbBuffers& b, Control* ctl, uint32_t repair_grid,
                          hipStream_t stream) {
-  hipLaunchKernelGGL(k_wb_mid, dim3(1), dim3(kWbMidBlock), 0, stream, n, seed, n_chunks, attempt,
+  const uint64_t ct = wb_tiles(n_chunks), rt = wb_tiles(b.rem_blocks);
+  if (ct == 0 || ct > kWbMaxTiles || rt == 0 || rt > kWbMaxTiles) return hipErrorInvalidValue;
+  const dim3 blk(kWbMidBlock);
+  hipLaunchKernelGGL(k_wb_tile_sums, dim3(static_cast<uint32_t>(ct)), blk, 0, stream, b.cnt,
+                     n_chunks, b.tsum, b, attempt, 0);
+  hipLaunchKernelGGL(k_wb_mid, dim3(1), blk, 0, stream, n, static_cast<uint32_t>(ct), attempt,
                      last, b, ctl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wb_tile_apply<uint64_t>, dim3(static_cast<uint32_t>(ct)), blk, 0, stream,
+                     b.cnt, b.off, n_chunks, b.tsum, b, attempt, 0);
   hipLaunchKernelGGL(k_wb_repair1, dim3(repair_grid), dim3(256), 0, stream, n, seed, attempt, b);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_wb_finish, dim3(1), dim3(kWbMidBlock), 0, stream, n, seed, attempt, b);
+  hipLaunchKernelGGL(k_wb_finish, dim3(1), blk, 0, stream, n, seed, attempt, b);
+  hipLaunchKernelGGL(k_wb_tile_sums, dim3(static_cast<uint32_t>(rt)), blk, 0, stream, b.rem,
+                     b.rem_blocks, b.tsum + kWbMaxTiles, b, attempt, 1);
+  hipLaunchKernelGGL(k_wb_rem_top, dim3(1), blk, 0, stream, static_cast<uint32_t>(rt), attempt, b);
+  hipLaunchKernelGGL(k_wb_tile_apply<uint32_t>, dim3(static_cast<uint32_t>(rt)), blk, 0, stream,
+                     b.rem, b.rem, b.rem_blocks, b.tsum + kWbMaxTiles, b, attempt, 1);
   return hipGetLastError();
 }
 

@@ -237,7 +237,14 @@ struct WbBuffers {
   uint64_t rem_blocks;
   unsigned long long* bitmap;
   uint64_t words;
+  uint64_t* tsum;  // kWbTileSums per-tile sums: the chunk counts', then the removal counts'
 };
+// The scans of the chunk counts and of the removal counts run over tiles of
+// kWbTile entries: per-tile sums on the whole grid, their scan in one
+// work-group, then each tile's scan offset by its sum's prefix.
+constexpr uint32_t kWbTile = 4096;
+constexpr uint32_t kWbMaxTiles = 512;  // per scan: up to 2^21 entries
+constexpr uint32_t kWbTileSums = 2 * kWbMaxTiles;
 // Zero the state, removal counts and bitmap; start the control block.
 hipError_t launch_wb_zero(Control* ctl, const WbBuffers& b, uint64_t n_chunks, unsigned int* err,
                           hipStream_t stream);
@@ -251,6 +258,8 @@ hipError_t launch_wb_count(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n
 hipError_t launch_wb_mid(uint64_t n, uint64_t seed, uint64_t n_chunks, uint32_t attempt, int last,
                          const WbBuffers& b, Control* ctl, uint32_t repair_grid,
                          hipStream_t stream);
+// Tiles a scan of `count` entries takes (at most kWbMaxTiles).
+inline uint64_t wb_tiles(uint64_t count) { return (count + kWbTile - 1) / kWbTile; }
 hipError_t launch_wb_write(uint64_t N, uint64_t seed, uint64_t chunk, uint64_t n_chunks, float c32,
                            int full, uint32_t attempt, const WbBuffers& b, uint64_t* out,
                            uint32_t grid, hipStream_t stream);
