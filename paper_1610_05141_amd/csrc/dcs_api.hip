@@ -459,8 +459,10 @@ void timing_end(hipStream_t s, Timing* t) {
 // Leaves of at most 1024 values need, when the range-forced levels end with
 // nodes of 2 n0 or more values and n0 = 4096, a split of such a node to leave
 // a quarter of its expected share.  One-pass leaves (n_v^2 >= 2 N_v with
-// n_v > 1024) need a density of 2/n0 or more, 16 times the sample's (kept
-// below 1/(32 n0)).
+// 1024 < n_v < n0) exist only for n0 > 1025; when N >= n n0, the expected
+// count n N_v / N of such a leaf's range is at most n_v^2 / (2 n0) < n_v / 2,
+// so n_v lies more than n_v / 2 above it: over sqrt(n_v / 2) > 22 standard
+// deviations.
 uint32_t mixed_takes(const Instance& I) {
   uint32_t forced = 0;
   while (ceil_div_pow2(I.N, forced) > kLeafRange) ++forced;
@@ -468,7 +470,7 @@ uint32_t mixed_takes(const Instance& I) {
   uint32_t takes = 0;
   if (I.variant == 1 || (I.n0 >= 1024 && n * 128u * I.dense_ratio < N)) takes |= dcs::kTakesDense;
   if (I.n0 >= 4096 && (I.n >> forced) >= 2ull * I.n0) takes |= dcs::kTakesSmall;
-  if (I.variant == 1 || n * 32u * I.n0 < N) takes |= dcs::kTakesOnce;
+  if (I.variant == 1 || I.n0 <= 1025 || n * I.n0 <= N) takes |= dcs::kTakesOnce;
   return takes;
 }
 
