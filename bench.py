@@ -36,12 +36,12 @@ BYTES_PER_SAMPLE = 8
 # while the sources still match it.
 TRAFFIC_SOURCES_SHA256 = "431c57e9dcd1f5baf469f65b8ad6f8d117199f33f06d809519e880a0cee3b159"
 LEAF_TRAFFIC = {  # k_leaf_pow2, n = 2^30 of N = 2^48
-    "fetch_bytes": 70_739_514,      # 34540.8 KiB FETCH_SIZE x 2.0
-    "write_bytes": 8_877_676_140,   # 8669605.6 KiB WRITE_SIZE x 1.0
+    "fetch_bytes": 70_600_684,      # 34473.0 KiB FETCH_SIZE x 2.0
+    "write_bytes": 8_877_810_144,   # 8669736.5 KiB WRITE_SIZE x 1.0
 }
 CONFIG_TRAFFIC = {
-    "c1_wor_2^20_of_2^32": {"kernel": "k_leaf_pow2", "fetch_bytes": 655_506,
-        "write_bytes": 12_134_176, "algorithmic_bytes": 8_388_608},
+    "c1_wor_2^20_of_2^32": {"kernel": "k_leaf_pow2", "fetch_bytes": 655_498,
+        "write_bytes": 12_126_592, "algorithmic_bytes": 8_388_608},
     "c2b_wor_dense_2^29_of_2^30": {"kernel": "k_leaf_dense", "fetch_bytes": 38_056_652,
         "write_bytes": 4_827_417_770, "algorithmic_bytes": 4_294_967_296},
     "c3a_bernoulli_p0.01_of_2^36": {"kernel": "k_bern_wave", "fetch_bytes": 227_996_353,
@@ -246,12 +246,19 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
                        "k_leaf_small": 12, "k_leaf_once": 13}
         run()
         dcs.synchronize(stream)
-        dcs.profile_enable(True)
+        # calls of small samples last tens of microseconds: time more of them
+        creps = reps if kind in ("bern", "wb") or args[0] >= (1 << 24) else 40 * reps
         t0 = time.perf_counter()
+        for _ in range(creps):
+            run()
+        dcs.synchronize(stream)
+        dt = (time.perf_counter() - t0) / creps
+        # kernel durations from `reps` more calls, with HIP events around
+        # every kernel (outside the timed calls, whose launches they would slow)
+        dcs.profile_enable(True)
         for _ in range(reps):
             run()
         dcs.synchronize(stream)
-        dt = (time.perf_counter() - t0) / reps
         avgs = {}
         for kname, kind_id in kernels.items():
             k_ms, k_n = dcs.profile_read(kind_id)
