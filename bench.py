@@ -286,6 +286,28 @@ def bench_other_configs(dcs, reps: int = 5, only=None):
     return res
 
 
+def time_calls(dcs, run, reps, stream, kinds=()):
+    """(seconds per call, {kind: (ms, launches)}, the last call's result):
+    `reps` calls back to back with no HIP events, then, for the kernel
+    durations of `kinds`, `reps` more with events around every kernel (the
+    events slow the launches of short calls, so they stay out of the timing)."""
+    dcs.synchronize(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        last = run()
+    dcs.synchronize(stream)
+    dt = (time.perf_counter() - t0) / reps
+    prof = {}
+    if kinds:
+        dcs.profile_enable(True)
+        for _ in range(reps):
+            run()
+        dcs.synchronize(stream)
+        prof = {k: dcs.profile_read(k) for k in kinds}
+        dcs.profile_enable(False)
+    return dt, prof, last
+
+
 def bench_parts(dcs, depths=(4, 8), reps: int = 3):
     """Online sampling in parts (Sec. 4.1): the n = 2^30 of 2^48 sample
     produced part by part, all 2^d parts of the depth-d cut in order, into
@@ -319,16 +341,8 @@ def bench_parts(dcs, depths=(4, 8), reps: int = 3):
                                 stream=stream, n0=N0)
 
         sweep()
-        dcs.synchronize(stream)
-        dcs.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            sweep()
-        dcs.synchronize(stream)
-        dt = (time.perf_counter() - t0) / reps
-        t_ms, t_n = dcs.profile_read(1)
-        l_ms, l_n = dcs.profile_read(2)
-        dcs.profile_enable(False)
+        dt, prof, _ = time_calls(dcs, sweep, reps, stream, (1, 2))
+        (t_ms, t_n), (l_ms, l_n) = prof[1], prof[2]
         count, rank = (int(x) for x in cr.cpu())
         res[f"depth_{d}"] = {
             "parts": 1 << d,
@@ -360,16 +374,8 @@ def bench_parts(dcs, depths=(4, 8), reps: int = 3):
             return total
 
         sweep()
-        dcs.synchronize(stream)
-        dcs.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            total = sweep()
-        dcs.synchronize(stream)
-        dt = (time.perf_counter() - t0) / reps
-        t_ms, t_n = dcs.profile_read(1)
-        l_ms, l_n = dcs.profile_read(2)
-        dcs.profile_enable(False)
+        dt, prof, total = time_calls(dcs, sweep, reps, stream, (1, 2))
+        (t_ms, t_n), (l_ms, l_n) = prof[1], prof[2]
         calls = (1 << d) // run
         res[f"session_depth_{d}_run_{run}"] = {
             "parts": 1 << d,
@@ -412,18 +418,11 @@ def bench_segments(dcs, reps: int = 5):
     }
     for name, (run, kinds) in cases.items():
         run()
-        dcs.synchronize(stream)
-        dcs.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            run()
-        dcs.synchronize(stream)
-        dt = (time.perf_counter() - t0) / reps
+        dt, prof, _ = time_calls(dcs, run, reps, stream, tuple(kinds.values()))
         r = {"ms_per_call": dt * 1e3, "samples_per_s": n / dt}
         for key, kind in kinds.items():
-            k_ms, k_n = dcs.profile_read(kind)
+            k_ms, k_n = prof[kind]
             r[key] = k_ms / max(k_n, 1)
-        dcs.profile_enable(False)
         res[name] = r
     d = out[1:] - out[:-1]
     res["invariants_ok"] = bool((d > 0).all()) and int(out[0]) >= 1 and int(out[-1]) <= N
@@ -459,15 +458,8 @@ def bench_graph(dcs, reps: int = 5):
     }
     for name, (run, count) in cases.items():
         run()
-        dcs.synchronize(stream)
-        dcs.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            run()
-        dcs.synchronize(stream)
-        dt = (time.perf_counter() - t0) / reps
-        d_ms, d_n = dcs.profile_read(7)
-        dcs.profile_enable(False)
+        dt, prof, _ = time_calls(dcs, run, reps, stream, (7,))
+        d_ms, d_n = prof[7]
         edges = m if count is None else (count if isinstance(count, int) else int(count.item()))
         dec = d_ms / max(d_n, 1)
         res[name] = {
