@@ -20,6 +20,10 @@ CASES = [
     (0, 1 << 20, 20 * (1 << 20) + 12345, 64, 4096),  # sparse leaves expected to repeat
     (0, 1 << 22, 1 << 40, 65, 4096),              # power-of-two ranges (front list)
     (1, 300_000, 3, 66, 4096),                    # constant leaves cut into pieces
+    # around N = n n0, where a single call stops launching the one-pass kernel
+    (0, 1 << 20, (1 << 31) + 11, 67, 4096),       # N = n n0 / 2: one-pass leaves
+    (0, 1 << 20, 1 << 32, 68, 4096),              # N = n n0: none expected
+    (0, 300_000, 300_000 * 1500 - 1, 69, 1500),   # just below n n0
 ]
 
 

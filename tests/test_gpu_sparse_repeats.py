@@ -104,6 +104,34 @@ def test_one_pass_paths_are_exercised(ref, case):
         assert rounds > 0, (done, rounds)
 
 
+def one_pass_leaves(ref, n, N, seed, n0, dense_ratio):
+    """Sparse leaves of the canonical tree that the one-pass kernel takes."""
+    return [(node, Nv, nv) for node, Nv, nv in leaves(ref, n, N, seed, n0, dense_ratio)
+            if nv > SMALL_MAX and nv * nv >= 2 * Nv]
+
+
+@pytest.mark.parametrize("n,N,seed,n0,dr", [
+    (1 << 20, 1 << 32, 71, 4096, 16),
+    (1 << 20, (1 << 32) + 12345, 72, 4096, 4),
+    (1 << 18, 1500 * (1 << 18), 73, 1500, 16),
+    (1 << 19, 3 * 4096 * (1 << 19) // 2, 74, 4096, 16),
+])
+def test_no_one_pass_leaf_when_N_is_at_least_n_n0(ref, n, N, seed, n0, dr):
+    """CPU only: a single call with N >= n n0 does not launch the one-pass
+    kernel, since such a leaf would need a count more than twice its range's
+    expectation; the canonical trees agree (the general kernel would take any
+    such leaf, so this decides only the work, never the sample)."""
+    assert N >= n * n0
+    assert one_pass_leaves(ref, n, N, seed, n0, dr) == []
+
+
+def test_one_pass_leaves_below_the_threshold(ref):
+    """CPU only: the check above can fail: at N = n n0 / 4 the tree has
+    one-pass leaves."""
+    n, n0 = 1 << 20, 4096
+    assert len(one_pass_leaves(ref, n, n * n0 // 4, 75, n0, 16)) > 0
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_repeating_sparse_leaves_match_oracle(ref, case):
