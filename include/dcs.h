@@ -463,7 +463,8 @@ int32_t dcs_debug_lookback_help(uint32_t polls);
  * a sample.  DCS_EINVAL above 8256 words. */
 int32_t dcs_debug_bernoulli_list(uint32_t words);
 /* dcs_debug_leaf_kernels -- test hook: which specialised leaf kernels a
- * single-instance tree call leaves out, their leaves then run in the general
+ * single-instance tree call (or a call of an online session, whose parts
+ * are subtrees of one sample's tree) leaves out, their leaves then run in the general
  * work-group kernel: bit 0 the one-wave dense kernel, bit 1 the one-wave
  * kernel of leaves of at most 1024 values, bit 2 the one-pass kernel of
  * leaves expected to repeat.  By default (mask < 0) a call leaves out the

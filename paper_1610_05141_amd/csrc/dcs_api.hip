@@ -478,7 +478,8 @@ uint32_t mixed_takes(const Instance& I) {
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
-                          unsigned int* err, uint32_t leaf_wgs_per_cu, uint64_t* part_out) {
+                          unsigned int* err, uint32_t leaf_wgs_per_cu, uint64_t* part_out,
+                          const Instance* whole) {
   if (leaf_cap >= dcs::kMaxLeafJobs) return DCS_ENOMEM;
   char* base = static_cast<char*>(ws);
   Control* ctl = reinterpret_cast<Control*>(base + L.ctl);
@@ -503,11 +504,12 @@ int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Ins
   uint64_t want = static_cast<uint64_t>(c->cus) * std::max<uint32_t>(1, leaf_wgs_per_cu);
   if (c->leaf_grid > 0) want = static_cast<uint64_t>(c->leaf_grid);
   want = std::max<uint64_t>(1, std::min<uint64_t>(want, leaf_cap));
-  // batches launch every leaf kernel; a single instance skips those whose
-  // kinds its tree cannot plausibly hold
-  uint32_t takes = (single != nullptr && n_inst == 1) ? mixed_takes(*single) : 0u;
+  // batches launch every leaf kernel; a single instance, or the parts of
+  // one sample, skip those whose kinds the sample's tree cannot plausibly hold
+  if (whole == nullptr && single != nullptr && n_inst == 1) whole = single;
+  uint32_t takes = whole != nullptr ? mixed_takes(*whole) : 0u;
   const int32_t forced_takes = g_debug_takes.load();
-  if (forced_takes >= 0 && single != nullptr && n_inst == 1) takes = static_cast<uint32_t>(forced_takes);
+  if (forced_takes >= 0 && whole != nullptr) takes = static_cast<uint32_t>(forced_takes);
   Timing t4{}, t5{};
   timing_begin(2, s, &t2);
   timing_begin(4, s, &t4);
@@ -1267,8 +1269,16 @@ int32_t dcs_online_next(dcs_online* o, uint64_t first, uint64_t count, uint64_t*
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = stage_upload(c, tab.data(), sizeof(Instance) * n_inst, static_cast<char*>(ws) + L.inst, s);
   if (rc) return rc;
+  // the parts are subtrees of the whole sample's tree
+  Instance whole{};
+  whole.n = o->n;
+  whole.N = o->N;
+  whole.seed = o->seed;
+  whole.n0 = o->P.n0;
+  whole.dense_ratio = o->P.dense_ratio;
+  whole.variant = v;
   return run_tree_pipeline(c, ws, L, nullptr, n_inst, tb, tt, leaf_cap, stack_depth, out_dev, s,
-                           error_word(c, stream), leaf_wgs_for(c, v, total));
+                           error_word(c, stream), leaf_wgs_for(c, v, total), nullptr, &whole);
 }
 
 int32_t dcs_online_destroy(dcs_online* o) {

@@ -112,11 +112,14 @@ int32_t device_ctx(DeviceCtx** out);
 // holds lock().
 // Leaf work-groups: DCS_LEAF_GRID if set, else cus * leaf_wgs_per_cu (both
 // leaf kernels use it).
+// whole: an instance whose canonical tree holds every leaf of the launch
+// (the sample whose parts the instances are); with `single` it decides which
+// specialised leaf kernels can be left out.
 int32_t run_tree_pipeline(DeviceCtx* c, void* ws, const TreeLayout& L, const Instance* single,
                           uint32_t n_inst, uint64_t threads, uint64_t top_threads,
                           uint64_t leaf_cap, uint32_t stack_depth, uint64_t* out, hipStream_t s,
                           unsigned int* err, uint32_t leaf_wgs_per_cu,
-                          uint64_t* part_out = nullptr);
+                          uint64_t* part_out = nullptr, const Instance* whole = nullptr);
 
 // Kernel timing with pooled HIP events on the launch stream (dcs_profile_*):
 // kinds as listed at dcs_profile_read; caller holds lock().

@@ -53,3 +53,36 @@ def test_leaf_kernel_mask_rejected_above_limit():
     with pytest.raises(mod.DcsError):
         mod.debug_leaf_kernels(8)
     mod.debug_leaf_kernels(-1)
+
+
+SESSION_CASES = [
+    # (variant, n, N, seed, n0, depth): parts of samples with the leaf kinds above
+    (0, 1 << 20, 1 << 21, 81, 4096, 6),               # dense leaves
+    (0, 1 << 20, 20 * (1 << 20) + 12345, 82, 4096, 5),  # sparse leaves expected to repeat
+    (0, 200_000, 10**9 + 7, 83, 512, 7),              # sparse leaves of 256-511 values
+    (1, 200_000, 10**9 + 7, 84, 512, 4),              # with-replacement leaves
+]
+
+
+@pytest.mark.parametrize("case", range(len(SESSION_CASES)))
+def test_leaf_kernel_choice_in_sessions(ref, m, case):
+    """An online session's calls are subtrees of one sample's tree and leave
+    out the same kernels as the whole sample's call; forced either way, and
+    by default, every part read in runs of 3 equals the oracle's sample."""
+    import torch
+    variant, n, N, seed, n0, depth = SESSION_CASES[case]
+    want = ref.replacement(n, N, seed, n0=n0) if variant else ref.sample(n, N, seed, n0=n0)
+    for mask in (0, 7, -1):
+        m.debug_leaf_kernels(mask)
+        announce(f"session leaf kernels mask {mask}: variant={variant} n={n} N={N} "
+                 f"seed={seed} n0={n0} depth={depth}")
+        o = m.Online(n, N, seed, depth, variant=variant, n0=n0)
+        buf = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+        pos = 0
+        for g in range(0, o.parts, 3):
+            pos += o.next(g, min(3, o.parts - g), buf[pos:])
+        m.synchronize()
+        o.close()
+        assert pos == n
+        got = to_np_u64(buf)
+        assert np.array_equal(got, want), (mask, first_mismatch(got, want))
