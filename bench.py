@@ -42,14 +42,14 @@ LEAF_TRAFFIC = {  # k_leaf_pow2, n = 2^30 of N = 2^48
 CONFIG_TRAFFIC = {
     "c1_wor_2^20_of_2^32": {"kernel": "k_leaf_pow2", "fetch_bytes": 655_498,
         "write_bytes": 12_126_592, "algorithmic_bytes": 8_388_608},
-    "c2b_wor_dense_2^29_of_2^30": {"kernel": "k_leaf_dense", "fetch_bytes": 38_056_652,
-        "write_bytes": 4_827_417_770, "algorithmic_bytes": 4_294_967_296},
-    "c3a_bernoulli_p0.01_of_2^36": {"kernel": "k_bern_wave", "fetch_bytes": 227_996_353,
-        "write_bytes": 5_893_695_786, "algorithmic_bytes": 5_497_618_384},
-    "c3b_wr_2^28_of_2^40": {"kernel": "k_leaf_pow2", "fetch_bytes": 23_134_518,
-        "write_bytes": 2_228_373_525, "algorithmic_bytes": 2_147_483_648},
-    "c2b_wholerange_B_2^29_of_2^30": {"kernel": "k_wb_write", "fetch_bytes": 171_998_264,
-        "write_bytes": 4_671_127_157, "algorithmic_bytes": 4_362_099_332},
+    "c2b_wor_dense_2^29_of_2^30": {"kernel": "k_leaf_dense", "fetch_bytes": 38_021_868,
+        "write_bytes": 4_831_421_120, "algorithmic_bytes": 4_294_967_296},
+    "c3a_bernoulli_p0.01_of_2^36": {"kernel": "k_bern_wave", "fetch_bytes": 228_354_369,
+        "write_bytes": 5_894_884_217, "algorithmic_bytes": 5_497_618_384},
+    "c3b_wr_2^28_of_2^40": {"kernel": "k_leaf_pow2", "fetch_bytes": 23_125_584,
+        "write_bytes": 2_228_530_617, "algorithmic_bytes": 2_147_483_648},
+    "c2b_wholerange_B_2^29_of_2^30": {"kernel": "k_wb_write", "fetch_bytes": 171_987_807,
+        "write_bytes": 4_669_660_403, "algorithmic_bytes": 4_362_099_332},
 }
 KERNEL_SOURCES = ("dcs_kernels.hip", "dcs_kernels.hpp", "dcs_device.hpp")
 
